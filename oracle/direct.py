@@ -1,0 +1,50 @@
+"""O1: direct evaluation of the Laplace potential (Eq. 1, section "The Fast
+Multipole Method").
+
+    phi_j = sum_{i, x_i != x_j} q_i / (4 pi |x_i - x_j|)
+
+Self-interaction is excluded.  For general (distinct) source and target
+arrays the excluded pairs are exactly those at distance zero: a target that
+coincides bitwise with a source does not see that source.
+
+Test infrastructure only (see the package docstring).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+INV_4PI = 1.0 / (4.0 * np.pi)
+
+
+def kernel_matrix(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """K[i, j] = 1 / (4 pi |x_i - y_j|), and 0 where x_i == y_j (Eq. 1).
+
+    x: (m, 3) evaluation points, y: (n, 3) source points, both float64.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    dx = x[:, None, 0] - y[None, :, 0]
+    dy = x[:, None, 1] - y[None, :, 1]
+    dz = x[:, None, 2] - y[None, :, 2]
+    r2 = dx * dx + dy * dy + dz * dz
+    with np.errstate(divide="ignore"):
+        k = INV_4PI / np.sqrt(r2)
+    k[r2 == 0.0] = 0.0
+    return k
+
+
+def direct(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
+           chunk: int = 2048) -> np.ndarray:
+    """Potentials at tgt due to charges at src, by the O(N^2) sum of Eq. (1).
+
+    src (n_src, 3), tgt (n_tgt, 3) float64; charges (n_src,) or (n_rhs, n_src).
+    Returns (n_tgt,) or (n_rhs, n_tgt) float64, matching the charges' rank.
+    """
+    q = np.asarray(charges, dtype=np.float64)
+    one = q.ndim == 1
+    q2 = q[None, :] if one else q
+    out = np.zeros((q2.shape[0], len(tgt)))
+    for s in range(0, len(tgt), chunk):
+        k = kernel_matrix(tgt[s:s + chunk], src)
+        out[:, s:s + chunk] = (k @ q2.T).T
+    return out[0] if one else out
