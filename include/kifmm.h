@@ -1,0 +1,198 @@
+/*
+ * kifmm.h -- C ABI of the MI355X kernel-independent FMM evaluation library.
+ *
+ * Computes the Laplace potential of Eq. (1) of the paper (section "The Fast
+ * Multipole Method"),
+ *
+ *     phi_j = sum_{i : y_i != x_j} q_i / (4 pi |y_i - x_j|),
+ *
+ * at every target x_j due to every source y_i, with the kernel-independent
+ * FMM: P2M, M2M, M2L (V list), P2L (X list), L2L, L2P, M2P (W list) and the
+ * near field (U list) over an octree, on check and equivalent surfaces of
+ * n_e = 6(p-1)^2 + 2 points (section "Computational structure of FMM
+ * operators").  The evaluation runs on the current HIP device.
+ *
+ * Conventions for every entry point:
+ *   - Return KIFMM_OK or an error status; on error, kifmm_last_error() holds
+ *     a message for the calling thread and no output buffer has been written
+ *     (except where stated).  No entry point aborts or throws.
+ *   - The caller owns every buffer it passes.  The library never frees a
+ *     caller buffer and keeps no caller pointer after returning.
+ *   - Points are row-major [n][3] float64 host arrays.  Charges and
+ *     potentials are row-major [n_rhs][n] arrays in the CALLER's order.
+ *   - Trees and operator sets are opaque library-owned handles released by
+ *     their *_destroy function.  A handle may be used from one thread at a
+ *     time; calls that overlap on one handle race.
+ */
+#ifndef KIFMM_H
+#define KIFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KIFMM_OK = 0,
+  KIFMM_EINVAL = 1,       /* bad argument: null pointer, size, non-finite, range */
+  KIFMM_ENOMEM = 2,       /* host or device allocation failed */
+  KIFMM_EDEVICE = 3,      /* a HIP runtime call failed (message has its text) */
+  KIFMM_EUNSUPPORTED = 4  /* valid request this build does not implement */
+} kifmm_status;
+
+/* Arithmetic of an evaluation.  In every mode the check-to-equivalent solves
+ * (UC2E, DC2E) run in FP64 and the per-target sum of near and far field is
+ * accumulated in FP64. */
+typedef enum {
+  KIFMM_FP64 = 0,        /* every operator in FP64 */
+  KIFMM_FP32 = 1,        /* particle operators, M2M, L2L, M2L in FP32 */
+  KIFMM_M2L_BF16X3 = 2,  /* as FP32; M2L as A_h x_h + A_h x_l + A_l x_h, BF16
+                            MFMA products accumulated in FP32 */
+  KIFMM_M2L_BF16X5 = 3   /* as FP32; M2L with the density split three ways:
+                            A_h x_h + A_h x_m + A_l x_h + A_l x_m + A_h x_l */
+} kifmm_precision;
+
+/* Octree parameters (section "Computational structure of FMM operators":
+ * n_crit is the leaf capacity; the 2:1 balance condition).  All geometric
+ * decisions are taken in FP64:
+ *   root: (root_center, root_halfwidth) if root_halfwidth > 0, else the
+ *     bounding cube of all points, centre (min+max)/2, half-width
+ *     max extent/2 * (1 + 2^-20);
+ *   level-l box index of a point: clamp(floor(t * 2^l), 0, 2^l - 1) per axis,
+ *     t = (x - (c0 - r0)) / (2 r0). */
+typedef struct {
+  int32_t uniform_depth; /* >= 0: uniform tree, every non-empty box split down to
+                            this level; -1: adaptive tree */
+  int32_t ncrit;         /* adaptive: split a box holding more than ncrit sources
+                            or more than ncrit targets (>= 1) */
+  int32_t max_depth;     /* adaptive: deepest level, 0..20 */
+  int32_t balance;       /* adaptive: 1 = enforce 2:1 balance between touching
+                            leaves (face, edge or corner), 0 = off */
+  double root_center[3];
+  double root_halfwidth; /* > 0 to fix the root cube; 0 = derive from the points */
+} kifmm_tree_params;
+
+typedef struct kifmm_tree kifmm_tree;
+typedef struct kifmm_ops kifmm_ops;
+
+/* Summary of a built tree (counts of interaction-list entries over all boxes). */
+typedef struct {
+  int64_t n_src, n_tgt;
+  int32_t depth, n_boxes, n_leaves, reserved;
+  int64_t n_u, n_v, n_w, n_x;
+  double root_center[3];
+  double root_halfwidth;
+} kifmm_tree_info;
+
+/* Build the octree and the U, V, W, X interaction lists on the host.
+ * src_xyz [n_src][3], tgt_xyz [n_tgt][3]: host FP64, finite; n_src, n_tgt >= 1.
+ * tgt_xyz may alias src_xyz (then self-interaction is excluded, Eq. 1).
+ * The device copy is made on first use by an evaluate call, on the device that
+ * is current then.  EINVAL on bad input, ENOMEM on allocation failure. */
+kifmm_status kifmm_build_tree(const double* src_xyz, int64_t n_src,
+                              const double* tgt_xyz, int64_t n_tgt,
+                              const kifmm_tree_params* params, kifmm_tree** out);
+
+kifmm_status kifmm_tree_get_info(const kifmm_tree* tree, kifmm_tree_info* info);
+
+/* Copy the box table out (for inspection and tests).  Boxes are numbered
+ * level by level, Morton order within a level.  Every pointer may be NULL to
+ * skip that array; otherwise it must hold n_boxes entries ([n_boxes][3] for
+ * anchor, [n_boxes][2] for the half-open ranges into the sorted points). */
+kifmm_status kifmm_tree_export_boxes(const kifmm_tree* tree, int32_t* level,
+                                     int32_t* anchor, int32_t* parent,
+                                     int32_t* is_leaf, int64_t* src_range,
+                                     int64_t* tgt_range);
+
+/* Copy one interaction list out as CSR over boxes: which = 0 U, 1 V, 2 W, 3 X.
+ * offsets [n_boxes + 1]; items [offsets[n_boxes]] box ids (may be NULL to
+ * query the size through offsets only).  Lists skip source boxes that hold no
+ * source (their contribution is zero). */
+kifmm_status kifmm_tree_export_list(const kifmm_tree* tree, int32_t which,
+                                    int64_t* offsets, int32_t* items);
+
+/* Sorted-to-caller permutations: src_perm[i] is the caller index of the i-th
+ * sorted source (either pointer may be NULL). */
+kifmm_status kifmm_tree_export_perm(const kifmm_tree* tree, int64_t* src_perm,
+                                    int64_t* tgt_perm);
+
+/* Precompute the operators of order p (2 <= p <= 16) on the host in FP64:
+ * surfaces, UC2E/DC2E pseudo-inverses truncated at rcond * sigma_max
+ * (0 < rcond < 1), the 8 M2M and 8 L2L child operators and the 316 M2L
+ * offset operators, on a reference box; per-level scaling is applied in the
+ * evaluation (section "Parallelization strategies for FMM operators").
+ * The device copy is made on first use. */
+kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out);
+
+/* Copy an operator table out (tests): which = 0 surface [n][3], 1 UC2E [n][n],
+ * 2 DC2E [n][n], 3 M2M [8][n][n], 4 L2L [8][n][n], 5 M2L [316][n][n],
+ * 6 M2L offsets [316][3] (as doubles).  Row-major, reference box of
+ * half-width 1.  n_out is the number of doubles `out` can hold. */
+kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out,
+                              int64_t n_out);
+int32_t kifmm_ops_n(const kifmm_ops* ops); /* surface points n, or -1 */
+
+/* Evaluate the potentials.  charges: DEVICE [n_rhs][n_src] (caller order),
+ * potentials: DEVICE [n_rhs][n_tgt] (caller order), both FP64 if
+ * io_fp64 != 0, else FP32.  n_rhs >= 1.  Runs asynchronously on hip_stream
+ * (a hipStream_t; NULL = the default stream); inputs must stay valid and
+ * unmodified until the stream reaches the end of the work.  The first call
+ * for a (tree, ops, precision, n_rhs) allocates and uploads device state that
+ * is reused by later calls. */
+kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops,
+                            const void* charges, int32_t n_rhs, void* potentials,
+                            int32_t io_fp64, kifmm_precision precision,
+                            void* hip_stream);
+
+/* Evaluate n_prob independent problems (each its own tree, n_rhs = 1) in one
+ * pass: every operator runs as one launch over all problems.  charges[k],
+ * potentials[k]: device buffers of problem k, as in kifmm_evaluate.  The
+ * trees are treated as one forest and its device state is cached for the
+ * same ordered set of tree handles. */
+kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees,
+                                  const kifmm_ops* ops, const void* const* charges,
+                                  void* const* potentials, int32_t io_fp64,
+                                  kifmm_precision precision, void* hip_stream);
+
+/* Whole pipeline from host arrays: build an adaptive tree (ncrit 64, balanced),
+ * precompute order p with rcond 1e-9, evaluate in FP32 (precision KIFMM_FP32),
+ * copy the FP64 potentials back.  Synchronous.  src, q [n_src]; tgt, pot
+ * [n_tgt]; host memory. */
+kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n_src,
+                                   const double* tgt, int64_t n_tgt, int32_t p,
+                                   double* pot);
+
+/* Per-phase device timing of evaluate calls: when enabled, each phase of every
+ * later evaluate is bracketed by HIP events on the evaluation stream and its
+ * duration accumulated.  Phase names: kifmm_phase_name(i), i < kifmm_n_phases().
+ * kifmm_get_phase_times fills ms[i] (total milliseconds) and launches[i]
+ * (number of kernel launches of phase i), and resets the counters.  It
+ * synchronises the stream of the last evaluate. */
+kifmm_status kifmm_set_profiling(int32_t enable);
+int32_t kifmm_n_phases(void);
+const char* kifmm_phase_name(int32_t i);
+kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches);
+
+/* Copy an intermediate buffer of the last kifmm_evaluate on `tree` to the host
+ * as FP64 (inspection and per-operator tests).  which = 0 upward check
+ * potentials, 1 upward equivalent densities, 2 downward check potentials,
+ * 3 downward equivalent densities (each [n_boxes][n_rhs][n], box order of
+ * kifmm_tree_export_boxes, check potentials scaled by the box half-width),
+ * 4 potentials [n_rhs][n_tgt] in sorted target order.  fp64 and n_rhs select
+ * the cached evaluation (precision FP64 or not).  Synchronises the device.
+ * EINVAL if no such evaluation has run or n_out is too small. */
+kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t fp64,
+                                int32_t n_rhs, double* out, int64_t n_out);
+
+void kifmm_tree_destroy(kifmm_tree* tree);
+void kifmm_ops_destroy(kifmm_ops* ops);
+
+/* Message of the last non-OK status returned to the calling thread. */
+const char* kifmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KIFMM_H */

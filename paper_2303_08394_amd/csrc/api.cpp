@@ -1,0 +1,300 @@
+// The C ABI (include/kifmm.h): argument checks, handle ownership, caching of
+// device state, and translation of internal errors into status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "device.hpp"
+#include "forest.hpp"
+#include "host_tree.hpp"
+#include "precompute.hpp"
+
+struct kifmm_tree {
+  std::unique_ptr<kifmm::HostTree> host;
+  std::unique_ptr<kifmm::EvalState> state;  // single-tree forest + device state
+  int state_n = 0;  // operator size the cached forest was built for
+};
+
+struct kifmm_ops {
+  std::unique_ptr<kifmm::HostOps> host;
+  kifmm::OpsCache cache;
+};
+
+namespace kifmm {
+
+static thread_local std::string t_last_error;
+
+kifmm_status fail(kifmm_status st, const std::string& msg) {
+  t_last_error = msg;
+  return st;
+}
+
+// Batch forests, keyed by the ordered tree handles and the operator set.
+struct BatchKey {
+  std::vector<const kifmm_tree*> trees;
+  const kifmm_ops* ops;
+  bool operator<(const BatchKey& o) const {
+    if (ops != o.ops) return ops < o.ops;
+    return trees < o.trees;
+  }
+};
+static std::mutex g_batch_mu;
+static std::map<BatchKey, std::unique_ptr<EvalState>> g_batches;
+
+static void purge_batches(const kifmm_tree* t, const kifmm_ops* o) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (auto it = g_batches.begin(); it != g_batches.end();) {
+    bool hit = (o && it->first.ops == o) ||
+               (t && std::find(it->first.trees.begin(), it->first.trees.end(), t) != it->first.trees.end());
+    it = hit ? g_batches.erase(it) : std::next(it);
+  }
+}
+
+static int plan_width(int n_rhs) { return std::max(1, 64 / n_rhs); }
+
+template <class F>
+static kifmm_status guard(F&& f) {
+  try {
+    f();
+    return KIFMM_OK;
+  } catch (const Error& e) {
+    return fail(e.status, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(KIFMM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(KIFMM_EDEVICE, e.what());
+  } catch (...) {
+    return fail(KIFMM_EDEVICE, "unknown internal error");
+  }
+}
+
+static void check_eval_args(const kifmm_tree* tree, const kifmm_ops* ops, int32_t n_rhs,
+                            kifmm_precision prec) {
+  if (!tree || !ops) raise(KIFMM_EINVAL, "evaluate: null tree or ops handle");
+  if (n_rhs < 1) raise(KIFMM_EINVAL, "evaluate: n_rhs must be >= 1");
+  if (n_rhs > 64) raise(KIFMM_EUNSUPPORTED, "evaluate: at most 64 right-hand sides per call");
+  if (prec < KIFMM_FP64 || prec > KIFMM_M2L_BF16X5) raise(KIFMM_EINVAL, "evaluate: unknown precision");
+}
+
+}  // namespace kifmm
+
+using namespace kifmm;
+
+extern "C" {
+
+const char* kifmm_last_error(void) { return t_last_error.c_str(); }
+
+kifmm_status kifmm_build_tree(const double* src_xyz, int64_t n_src, const double* tgt_xyz,
+                              int64_t n_tgt, const kifmm_tree_params* params, kifmm_tree** out) {
+  if (!out) return fail(KIFMM_EINVAL, "build_tree: null output handle");
+  if (!params) return fail(KIFMM_EINVAL, "build_tree: null params");
+  return guard([&] {
+    auto t = std::make_unique<kifmm_tree>();
+    t->host.reset(build_host_tree(src_xyz, n_src, tgt_xyz, n_tgt, *params));
+    *out = t.release();
+  });
+}
+
+kifmm_status kifmm_tree_get_info(const kifmm_tree* tree, kifmm_tree_info* info) {
+  if (!tree || !info) return fail(KIFMM_EINVAL, "tree_get_info: null argument");
+  const HostTree& T = *tree->host;
+  std::memset(info, 0, sizeof(*info));
+  info->n_src = T.nsrc;
+  info->n_tgt = T.ntgt;
+  info->depth = T.depth;
+  info->n_boxes = T.nbox;
+  info->n_leaves = int32_t(T.leaves.size());
+  info->n_u = int64_t(T.items[LIST_U].size());
+  info->n_v = int64_t(T.items[LIST_V].size());
+  info->n_w = int64_t(T.items[LIST_W].size());
+  info->n_x = int64_t(T.items[LIST_X].size());
+  for (int d = 0; d < 3; ++d) info->root_center[d] = T.c0[d];
+  info->root_halfwidth = T.r0;
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_tree_export_boxes(const kifmm_tree* tree, int32_t* level, int32_t* anchor,
+                                     int32_t* parent, int32_t* is_leaf, int64_t* src_range,
+                                     int64_t* tgt_range) {
+  if (!tree) return fail(KIFMM_EINVAL, "tree_export_boxes: null tree");
+  const HostTree& T = *tree->host;
+  for (int32_t b = 0; b < T.nbox; ++b) {
+    if (level) level[b] = T.level[b];
+    if (anchor)
+      for (int d = 0; d < 3; ++d) anchor[3 * b + d] = T.anchor[3 * b + d];
+    if (parent) parent[b] = T.parent[b];
+    if (is_leaf) is_leaf[b] = T.leaf[b];
+    if (src_range) {
+      src_range[2 * b] = T.sbeg[b];
+      src_range[2 * b + 1] = T.send[b];
+    }
+    if (tgt_range) {
+      tgt_range[2 * b] = T.tbeg[b];
+      tgt_range[2 * b + 1] = T.tend[b];
+    }
+  }
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_tree_export_list(const kifmm_tree* tree, int32_t which, int64_t* offsets,
+                                    int32_t* items) {
+  if (!tree || !offsets) return fail(KIFMM_EINVAL, "tree_export_list: null argument");
+  if (which < 0 || which > 3) return fail(KIFMM_EINVAL, "tree_export_list: which must be 0..3");
+  const HostTree& T = *tree->host;
+  std::copy(T.off[which].begin(), T.off[which].end(), offsets);
+  if (items) std::copy(T.items[which].begin(), T.items[which].end(), items);
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_tree_export_perm(const kifmm_tree* tree, int64_t* src_perm, int64_t* tgt_perm) {
+  if (!tree) return fail(KIFMM_EINVAL, "tree_export_perm: null tree");
+  const HostTree& T = *tree->host;
+  if (src_perm) std::copy(T.sperm.begin(), T.sperm.end(), src_perm);
+  if (tgt_perm) std::copy(T.tperm.begin(), T.tperm.end(), tgt_perm);
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out) {
+  if (!out) return fail(KIFMM_EINVAL, "precompute_operators: null output handle");
+  return guard([&] {
+    auto o = std::make_unique<kifmm_ops>();
+    o->host.reset(build_host_ops(p, rcond));
+    *out = o.release();
+  });
+}
+
+int32_t kifmm_ops_n(const kifmm_ops* ops) { return ops ? ops->host->n : -1; }
+
+kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out, int64_t n_out) {
+  if (!ops || !out) return fail(KIFMM_EINVAL, "ops_export: null argument");
+  const HostOps& H = *ops->host;
+  std::vector<double> off;
+  const std::vector<double>* v = nullptr;
+  switch (which) {
+    case 0: v = &H.surf; break;
+    case 1: v = &H.uc2e; break;
+    case 2: v = &H.dc2e; break;
+    case 3: v = &H.m2m; break;
+    case 4: v = &H.l2l; break;
+    case 5: v = &H.m2l; break;
+    case 6:
+      off.assign(H.m2l_offset.begin(), H.m2l_offset.end());
+      v = &off;
+      break;
+    default: return fail(KIFMM_EINVAL, "ops_export: which must be 0..6");
+  }
+  if (n_out < int64_t(v->size())) return fail(KIFMM_EINVAL, "ops_export: output too small");
+  std::copy(v->begin(), v->end(), out);
+  return KIFMM_OK;
+}
+
+kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const void* charges,
+                            int32_t n_rhs, void* potentials, int32_t io_fp64,
+                            kifmm_precision precision, void* hip_stream) {
+  return guard([&] {
+    check_eval_args(tree, ops, n_rhs, precision);
+    if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate: null charges or potentials");
+    auto* t = const_cast<kifmm_tree*>(tree);
+    const int TB = plan_width(n_rhs);
+    if (!t->state || t->state_n != ops->host->n || t->state->host->m2l.TB != TB) {
+      t->state.reset(new EvalState());
+      const HostTree* one = t->host.get();
+      t->state->host.reset(build_forest(&one, 1, *ops->host, TB));
+      t->state_n = ops->host->n;
+    }
+    const void* q[1] = {charges};
+    void* o[1] = {potentials};
+    evaluate_forest(*t->state, *ops->host, const_cast<kifmm_ops*>(ops)->cache, q, o, n_rhs,
+                    io_fp64 != 0, precision, hip_stream);
+  });
+}
+
+kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees,
+                                  const kifmm_ops* ops, const void* const* charges,
+                                  void* const* potentials, int32_t io_fp64,
+                                  kifmm_precision precision, void* hip_stream) {
+  return guard([&] {
+    if (n_prob < 1) raise(KIFMM_EINVAL, "evaluate_batch: n_prob must be >= 1");
+    if (!trees || !charges || !potentials) raise(KIFMM_EINVAL, "evaluate_batch: null array");
+    for (int k = 0; k < n_prob; ++k) {
+      check_eval_args(trees[k], ops, 1, precision);
+      if (!charges[k] || !potentials[k]) raise(KIFMM_EINVAL, "evaluate_batch: null buffer");
+    }
+    BatchKey key{std::vector<const kifmm_tree*>(trees, trees + n_prob), ops};
+    EvalState* st = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_batch_mu);
+      auto& slot = g_batches[key];
+      if (!slot) {
+        std::vector<const HostTree*> hts(n_prob);
+        for (int k = 0; k < n_prob; ++k) hts[k] = trees[k]->host.get();
+        auto s = std::make_unique<EvalState>();
+        s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1)));
+        slot = std::move(s);
+      }
+      st = slot.get();
+    }
+    evaluate_forest(*st, *ops->host, const_cast<kifmm_ops*>(ops)->cache, charges, potentials, 1,
+                    io_fp64 != 0, precision, hip_stream);
+  });
+}
+
+kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n_src,
+                                   const double* tgt, int64_t n_tgt, int32_t p, double* pot) {
+  if (!src || !q || !tgt || !pot) return fail(KIFMM_EINVAL, "evaluate_simple: null argument");
+  return guard([&] {
+    kifmm_tree_params prm{};
+    prm.uniform_depth = -1;
+    prm.ncrit = 64;
+    prm.max_depth = 20;
+    prm.balance = 1;
+    std::unique_ptr<HostTree> ht(build_host_tree(src, n_src, tgt, n_tgt, prm));
+    std::unique_ptr<HostOps> ho(build_host_ops(p, 1e-9));
+    for (int64_t i = 0; i < n_src; ++i)
+      if (!std::isfinite(q[i])) raise(KIFMM_EINVAL, "evaluate_simple: non-finite charge");
+    EvalState st;
+    const HostTree* one = ht.get();
+    st.host.reset(build_forest(&one, 1, *ho, plan_width(1)));
+    OpsCache oc;
+    evaluate_simple_host(st, *ho, oc, q, n_src, pot, n_tgt);
+  });
+}
+
+kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t fp64,
+                                int32_t n_rhs, double* out, int64_t n_out) {
+  if (!tree || !out) return fail(KIFMM_EINVAL, "debug_buffer: null argument");
+  return guard([&] {
+    if (!tree->state) raise(KIFMM_EINVAL, "debug_buffer: no evaluation has run on this tree");
+    debug_buffer(*tree->state, which, fp64 != 0, n_rhs, out, n_out);
+  });
+}
+
+void kifmm_tree_destroy(kifmm_tree* tree) {
+  if (!tree) return;
+  purge_batches(tree, nullptr);
+  delete tree;
+}
+
+void kifmm_ops_destroy(kifmm_ops* ops) {
+  if (!ops) return;
+  purge_batches(nullptr, ops);
+  delete ops;
+}
+
+kifmm_status kifmm_set_profiling(int32_t enable) {
+  set_profiling(enable != 0);
+  return KIFMM_OK;
+}
+int32_t kifmm_n_phases(void) { return n_phases(); }
+const char* kifmm_phase_name(int32_t i) { return phase_name(i); }
+kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches) {
+  return guard([&] { get_phase_times(ms, launches); });
+}
+
+}  // extern "C"

@@ -1,0 +1,60 @@
+// Device-side state of an evaluation: the forest and operator tables in HBM,
+// the work buffers, and the entry into the evaluation pipeline.
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "forest.hpp"
+#include "kifmm.h"
+
+namespace kifmm {
+
+struct DevPlan {
+  int32_t ntile = 0, TB = 0;
+  int32_t *tile_cols = nullptr, *step_beg = nullptr, *step_op = nullptr, *step_src = nullptr;
+  int64_t nstep = 0, useful_pairs = 0;
+};
+
+struct DevForest;   // defined in evaluate.hip
+struct DevOps;
+struct DevWork;
+
+// Everything one evaluation needs on one device: built on first use.
+struct EvalState {
+  int device = -1;
+  std::unique_ptr<HostForest> host;
+  DevForest* forest = nullptr;
+  ~EvalState();
+};
+
+// Uploads (once) and returns the device operator tables of `ops` for `device`.
+struct OpsCache {
+  std::map<int, DevOps*> per_device;
+  ~OpsCache();
+};
+
+// Runs the evaluation; throws kifmm::Error.
+void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& ocache,
+                     const void* const* charges, void* const* potentials, int n_rhs,
+                     bool io_fp64, kifmm_precision prec, void* stream);
+
+// Host-memory convenience: copies charges in, evaluates in FP32 with FP64
+// input/output on the default stream, copies potentials out, synchronously.
+void evaluate_simple_host(EvalState& st, const HostOps& hops, OpsCache& oc, const double* q,
+                          int64_t nsrc, double* pot, int64_t ntgt);
+
+// Copies a cached work buffer to the host as FP64 (see kifmm_debug_buffer).
+void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out);
+
+int current_device();
+
+// profiling
+void set_profiling(bool on);
+int n_phases();
+const char* phase_name(int i);
+void get_phase_times(double* ms, int64_t* launches);
+
+}  // namespace kifmm

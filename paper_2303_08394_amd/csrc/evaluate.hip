@@ -1,0 +1,1002 @@
+// KIFMM evaluation on one CDNA4 GPU: device state, kernels and the pipeline.
+//
+// Pipeline (sections "The Fast Multipole Method" and "Computational
+// structure of FMM operators"): gather charges into Morton order; P2M at the
+// leaves; M2M + UC2E level by level upward; P2L (X lists) and M2L (V lists)
+// for all levels in one launch each; L2L + DC2E level by level downward; one
+// fused leaf kernel for L2P + M2P (W lists) + near field (U lists) with the
+// per-target sum in FP64; scatter back to the caller's order.
+//
+// Units: coordinates are relative to a box centre in units of its half-width
+// r.  A "scaled" check potential is r times the check potential; with it every
+// translation operator is the same at all levels (the kernel is homogeneous
+// of degree -1), and the particle kernels work on O(1) numbers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "device.hpp"
+
+namespace kifmm {
+
+#define HIPCHECK(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      raise(KIFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));           \
+  } while (0)
+
+#define LAUNCHCHECK(what)                                                                \
+  do {                                                                                   \
+    hipError_t e_ = hipGetLastError();                                                   \
+    if (e_ != hipSuccess) raise(KIFMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static constexpr double kInv4Pi = 0.0795774715459476678844418816863;
+static constexpr double kRin = 1.05, kRout = 2.95;
+
+// ------------------------------------------------------------------------
+// device state
+// ------------------------------------------------------------------------
+
+struct DevOps {
+  int n = 0, ld = 0;
+  double *uc2e = nullptr, *dc2e = nullptr;               // [ld][ld]
+  float *m2m32 = nullptr, *l2l32 = nullptr, *m2l32 = nullptr;  // [k][ld][ld]
+  double *m2m64 = nullptr, *l2l64 = nullptr, *m2l64 = nullptr;
+  double4* surf = nullptr;                               // [n] unit-cube surface
+  std::vector<void*> allocs;
+  ~DevOps() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+struct DevWork {
+  int n_rhs = 0;
+  bool fp64 = false;
+  void* qs = nullptr;       // [n_rhs][nsrc]
+  void* up_chk = nullptr;   // [nbox][n_rhs][ld]
+  void* up_eq = nullptr;
+  void* dn_chk = nullptr;
+  void* dn_eq = nullptr;
+  double* pot = nullptr;    // [n_rhs][ntgt]
+  size_t col_bytes = 0;
+  std::vector<void*> allocs;
+  ~DevWork() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+struct DevForest {
+  int32_t nbox = 0, nprob = 0, depth = 0;
+  int64_t nsrc = 0, ntgt = 0;
+  int ld = 0, n = 0;
+  int4* box_geo = nullptr;
+  double* box_r = nullptr;
+  int2 *box_src = nullptr, *box_tgt = nullptr;
+  double4 *src64 = nullptr, *tgt64 = nullptr;
+  float4* tgt32 = nullptr;
+  int32_t *src_perm = nullptr, *tgt_perm = nullptr;
+  int64_t *src_off = nullptr, *tgt_off = nullptr;
+  int32_t *p2m_boxes = nullptr, *leaf_boxes = nullptr, *u_off = nullptr, *u_items = nullptr;
+  int32_t *w_off = nullptr, *w_items = nullptr, *x_boxes = nullptr, *x_off = nullptr, *x_items = nullptr;
+  int32_t n_p2m = 0, n_leaf = 0, n_x = 0;
+  int64_t max_src_per_prob = 0, max_tgt_per_prob = 0;
+  std::vector<DevPlan> m2m, uc2e, l2l, dc2e;
+  DevPlan m2l;
+  std::vector<void*> allocs;
+  std::map<std::pair<int, int>, DevWork*> work;  // (fp64, n_rhs)
+  ~DevForest() {
+    for (auto& w : work) delete w.second;
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+EvalState::~EvalState() { delete forest; }
+OpsCache::~OpsCache() {
+  for (auto& kv : per_device) delete kv.second;
+}
+
+int current_device() {
+  int d = 0;
+  HIPCHECK(hipGetDevice(&d));
+  return d;
+}
+
+template <class T>
+static T* dev_alloc(std::vector<void*>& allocs, size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  allocs.push_back(p);
+  return static_cast<T*>(p);
+}
+
+template <class D, class S>
+static D* dev_upload(std::vector<void*>& allocs, const std::vector<S>& v) {
+  static_assert(sizeof(D) % sizeof(S) == 0 || sizeof(S) % sizeof(D) == 0, "layout");
+  size_t bytes = v.size() * sizeof(S);
+  size_t count = (bytes + sizeof(D) - 1) / sizeof(D);
+  D* p = dev_alloc<D>(allocs, count);
+  if (bytes) HIPCHECK(hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice));
+  return p;
+}
+
+static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P) {
+  DevPlan d;
+  d.ntile = P.ntile;
+  d.TB = P.TB;
+  d.nstep = P.nstep();
+  d.useful_pairs = P.useful_pairs;
+  if (P.ntile == 0) return d;
+  d.tile_cols = dev_upload<int32_t>(allocs, P.tile_cols);
+  d.step_beg = dev_upload<int32_t>(allocs, P.step_beg);
+  d.step_op = dev_upload<int32_t>(allocs, P.step_op);
+  d.step_src = dev_upload<int32_t>(allocs, P.step_src);
+  return d;
+}
+
+static int round16(int n) { return (n + 15) / 16 * 16; }
+
+static DevForest* upload_forest(const HostForest& F, int n) {
+  auto* D = new DevForest();
+  try {
+    D->nbox = F.nbox;
+    D->nprob = F.nprob;
+    D->depth = F.depth;
+    D->nsrc = F.nsrc;
+    D->ntgt = F.ntgt;
+    D->n = n;
+    D->ld = round16(n);
+    auto& A = D->allocs;
+    D->box_geo = dev_upload<int4>(A, F.box_geo);
+    D->box_r = dev_upload<double>(A, F.box_r);
+    D->box_src = dev_upload<int2>(A, F.box_src);
+    D->box_tgt = dev_upload<int2>(A, F.box_tgt);
+    D->src64 = dev_upload<double4>(A, F.src_f64);
+    D->tgt64 = dev_upload<double4>(A, F.tgt_f64);
+    D->tgt32 = dev_upload<float4>(A, F.tgt_f32);
+    D->src_perm = dev_upload<int32_t>(A, F.src_perm);
+    D->tgt_perm = dev_upload<int32_t>(A, F.tgt_perm);
+    D->src_off = dev_upload<int64_t>(A, F.src_off);
+    D->tgt_off = dev_upload<int64_t>(A, F.tgt_off);
+    for (int k = 0; k < F.nprob; ++k) {
+      D->max_src_per_prob = std::max(D->max_src_per_prob, F.src_off[k + 1] - F.src_off[k]);
+      D->max_tgt_per_prob = std::max(D->max_tgt_per_prob, F.tgt_off[k + 1] - F.tgt_off[k]);
+    }
+    D->p2m_boxes = dev_upload<int32_t>(A, F.p2m_boxes);
+    D->n_p2m = int32_t(F.p2m_boxes.size());
+    D->leaf_boxes = dev_upload<int32_t>(A, F.leaf_boxes);
+    D->n_leaf = int32_t(F.leaf_boxes.size());
+    D->u_off = dev_upload<int32_t>(A, F.u_off);
+    D->u_items = dev_upload<int32_t>(A, F.u_items);
+    D->w_off = dev_upload<int32_t>(A, F.w_off);
+    D->w_items = dev_upload<int32_t>(A, F.w_items);
+    D->x_boxes = dev_upload<int32_t>(A, F.x_boxes);
+    D->n_x = int32_t(F.x_boxes.size());
+    D->x_off = dev_upload<int32_t>(A, F.x_off);
+    D->x_items = dev_upload<int32_t>(A, F.x_items);
+    for (auto& p : F.m2m) D->m2m.push_back(upload_plan(A, p));
+    for (auto& p : F.uc2e) D->uc2e.push_back(upload_plan(A, p));
+    for (auto& p : F.l2l) D->l2l.push_back(upload_plan(A, p));
+    for (auto& p : F.dc2e) D->dc2e.push_back(upload_plan(A, p));
+    D->m2l = upload_plan(A, F.m2l);
+  } catch (...) {
+    delete D;
+    throw;
+  }
+  return D;
+}
+
+// pads a row-major [k][n][n] table to [k][ld][ld] with zeros
+template <class T>
+static std::vector<T> pad_table(const std::vector<double>& src, int k, int n, int ld) {
+  std::vector<T> out(size_t(k) * ld * ld, T(0));
+  for (int m = 0; m < k; ++m)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        out[(size_t(m) * ld + i) * ld + j] = T(src[(size_t(m) * n + i) * n + j]);
+  return out;
+}
+
+static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64) {
+  DevOps*& O = oc.per_device[dev];
+  if (!O) {
+    O = new DevOps();
+    O->n = H.n;
+    O->ld = round16(H.n);
+    O->uc2e = dev_upload<double>(O->allocs, pad_table<double>(H.uc2e, 1, H.n, O->ld));
+    O->dc2e = dev_upload<double>(O->allocs, pad_table<double>(H.dc2e, 1, H.n, O->ld));
+    std::vector<double> s4(4 * size_t(H.n), 0.0);
+    for (int i = 0; i < H.n; ++i)
+      for (int d = 0; d < 3; ++d) s4[4 * i + d] = H.surf[3 * i + d];
+    O->surf = dev_upload<double4>(O->allocs, s4);
+  }
+  if (fp64 && !O->m2l64) {
+    O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8, H.n, O->ld));
+    O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8, H.n, O->ld));
+    O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
+  }
+  if (!fp64 && !O->m2l32) {
+    O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8, H.n, O->ld));
+    O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8, H.n, O->ld));
+    O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L, H.n, O->ld));
+  }
+  return O;
+}
+
+static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
+  DevWork*& W = F.work[{fp64 ? 1 : 0, n_rhs}];
+  if (W) return W;
+  W = new DevWork();
+  W->n_rhs = n_rhs;
+  W->fp64 = fp64;
+  size_t es = fp64 ? 8 : 4;
+  size_t cols = size_t(F.nbox) * n_rhs * F.ld;
+  W->col_bytes = cols * es;
+  auto alloc_bytes = [&](size_t bytes) {
+    void* p = dev_alloc<unsigned char>(W->allocs, bytes);
+    HIPCHECK(hipMemset(p, 0, bytes));
+    return p;
+  };
+  W->qs = alloc_bytes(size_t(n_rhs) * F.nsrc * es);
+  W->up_chk = alloc_bytes(W->col_bytes);
+  W->up_eq = alloc_bytes(W->col_bytes);
+  W->dn_chk = alloc_bytes(W->col_bytes);
+  W->dn_eq = alloc_bytes(W->col_bytes);
+  W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * F.ntgt * 8));
+  return W;
+}
+
+// ------------------------------------------------------------------------
+// profiling: HIP events around each phase on the evaluation stream
+// ------------------------------------------------------------------------
+
+enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L, PH_L2L, PH_DC2E, PH_LEAF, PH_SCATTER, PH_N };
+static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l",
+                                        "m2l", "l2l", "dc2e", "leaf", "scatter"};
+
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int ph;
+    hipEvent_t a, b;
+    int launches;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipStream_t stream = nullptr;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    return e;
+  }
+};
+static Profiler g_prof;
+
+struct PhaseScope {
+  int ph;
+  hipStream_t s;
+  hipEvent_t a{};
+  int launches = 0;
+  PhaseScope(int ph_, hipStream_t s_) : ph(ph_), s(s_) {
+    if (g_prof.on) {
+      a = g_prof.get();
+      HIPCHECK(hipEventRecord(a, s));
+    }
+  }
+  ~PhaseScope() noexcept(false) {
+    if (g_prof.on) {
+      hipEvent_t b = g_prof.get();
+      HIPCHECK(hipEventRecord(b, s));
+      g_prof.recs.push_back({ph, a, b, launches});
+      g_prof.stream = s;
+    }
+  }
+};
+
+void set_profiling(bool on) { g_prof.on = on; }
+int n_phases() { return PH_N; }
+const char* phase_name(int i) { return (i >= 0 && i < PH_N) ? kPhaseNames[i] : nullptr; }
+void get_phase_times(double* ms, int64_t* launches) {
+  for (int i = 0; i < PH_N; ++i) {
+    if (ms) ms[i] = 0;
+    if (launches) launches[i] = 0;
+  }
+  if (!g_prof.recs.empty()) HIPCHECK(hipEventSynchronize(g_prof.recs.back().b));
+  for (auto& r : g_prof.recs) {
+    float t = 0;
+    HIPCHECK(hipEventElapsedTime(&t, r.a, r.b));
+    if (ms) ms[r.ph] += t;
+    if (launches) launches[r.ph] += r.launches;
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.recs.clear();
+}
+
+// ------------------------------------------------------------------------
+// kernels
+// ------------------------------------------------------------------------
+
+template <class T> struct V4;
+template <> struct V4<float> { using type = float4; };
+template <> struct V4<double> { using type = double4; };
+
+__device__ inline float rinv(float r2) { return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f; }
+__device__ inline double rinv(double r2) { return r2 > 0.0 ? rsqrt(r2) : 0.0; }
+
+constexpr int kMaxProb = 64;
+struct PtrPack {
+  const void* p[kMaxProb];
+};
+
+template <class TI, class T>
+__global__ void gather_kernel(PtrPack q, int prob0, const int64_t* __restrict__ src_off,
+                              const int32_t* __restrict__ perm, int n_rhs, int64_t nsrc,
+                              T* __restrict__ qs) {
+  const int k = blockIdx.y;
+  const int64_t b = src_off[prob0 + k], e = src_off[prob0 + k + 1];
+  const int64_t i = b + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= e) return;
+  const int64_t nk = e - b;
+  const TI* src = static_cast<const TI*>(q.p[k]);
+  const int64_t ci = perm[i];
+  for (int r = 0; r < n_rhs; ++r) qs[int64_t(r) * nsrc + i] = T(src[int64_t(r) * nk + ci]);
+}
+
+template <class TO>
+__global__ void scatter_kernel(PtrPack out, int prob0, const int64_t* __restrict__ tgt_off,
+                               const int32_t* __restrict__ perm, int n_rhs, int64_t ntgt,
+                               const double* __restrict__ pot) {
+  const int k = blockIdx.y;
+  const int64_t b = tgt_off[prob0 + k], e = tgt_off[prob0 + k + 1];
+  const int64_t i = b + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= e) return;
+  const int64_t nk = e - b;
+  TO* dst = static_cast<TO*>(const_cast<void*>(out.p[k]));
+  const int64_t ci = perm[i];
+  for (int r = 0; r < n_rhs; ++r) dst[int64_t(r) * nk + ci] = TO(pot[int64_t(r) * ntgt + i]);
+}
+
+__global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += int64_t(gridDim.x) * blockDim.x)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+
+// --- P2P-shaped operators -------------------------------------------------
+// One block per target box.  Targets are particles (LEAF) or surface points
+// (P2M: upward check, P2L: downward check); sources are "segments": the
+// particles of a leaf, or the equivalent surface of a box with its density.
+// Every source is moved into the target box's frame once, while it is staged
+// into LDS; targets are split into chunks of TCH lanes and the SL = 256/TCH
+// lane groups ("slices") stride over the staged sources, then reduce in FP64.
+
+enum { MODE_P2M = 0, MODE_P2L = 1, MODE_LEAF = 2 };
+enum { SEG_POINTS = 0, SEG_UP_EQUIV = 1, SEG_DN_EQUIV = 2 };
+
+template <class T>
+struct P2PArgs {
+  const int4* box_geo;
+  const double* box_r;
+  const int2* box_src;
+  const int2* box_tgt;
+  const double4* src64;
+  const typename V4<T>::type* tgt;
+  const T* qs;
+  int64_t nsrc;
+  int n_rhs;
+  const double4* surf;
+  int n, ld;
+  const T* up_eq;
+  const T* dn_eq;
+  T* out_col;
+  double* pot;
+  int64_t ntgt;
+  const int32_t* work;
+  const int32_t* l1_off;
+  const int32_t* l1_items;
+  const int32_t* l2_off;
+  const int32_t* l2_items;
+};
+
+template <class T, int RC>
+struct P2PCfg {
+  static constexpr int NT = 256;
+  static constexpr int PB = int(sizeof(typename V4<T>::type)) + RC * int(sizeof(T));
+  // The batch size depends on T only, so every right-hand side sees the same
+  // summation order whatever RC is (multi-RHS columns equal single runs bitwise).
+  static constexpr int CAP = sizeof(T) == 4 ? 1024 : 512;
+  static constexpr int RED = NT * RC * 8;
+  static constexpr int SMEM = CAP * PB > RED ? CAP * PB : RED;
+  static constexpr int MAXSEG = 256;
+  static constexpr int NCH = 4;
+};
+
+// (A -> B) frame change: shift = (c_A - c_B) / r_B, ratio = r_A / r_B.
+__device__ inline double4 frame(int4 a, int4 b) {
+  double ratio = ldexp(1.0, b.w - a.w);
+  double4 g;
+  g.x = (2.0 * a.x + 1.0) * ratio - (2.0 * b.x + 1.0);
+  g.y = (2.0 * a.y + 1.0) * ratio - (2.0 * b.y + 1.0);
+  g.z = (2.0 * a.z + 1.0) * ratio - (2.0 * b.z + 1.0);
+  g.w = ratio;
+  return g;
+}
+
+template <class T, int MODE, int RC, int TCH>
+__global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
+  using C = P2PCfg<T, RC>;
+  using V = typename V4<T>::type;
+  constexpr int NT = C::NT, SL = NT / TCH, CAP = C::CAP, MAXSEG = C::MAXSEG, NCH = C::NCH;
+  __shared__ __align__(16) unsigned char smem[C::SMEM];
+  __shared__ int s_pre[MAXSEG + 1];
+  __shared__ int s_id[MAXSEG];
+  __shared__ int s_kind[MAXSEG];
+  __shared__ double4 s_geo[MAXSEG];
+  V* s_pos = reinterpret_cast<V*>(smem);
+  T* s_q = reinterpret_cast<T*>(smem + CAP * sizeof(V));
+  double* s_red = reinterpret_cast<double*>(smem);
+
+  const int tid = threadIdx.x, ti = tid % TCH, sl = tid / TCH;
+  const int wi = blockIdx.x;
+  const int B = a.work[wi];
+  const int rhs0 = blockIdx.y * RC;
+  const int4 gB = a.box_geo[B];
+
+  int nU = 0, nW = 0, nseg = 0;
+  if (MODE == MODE_P2M) {
+    nseg = 1;
+  } else if (MODE == MODE_P2L) {
+    nU = a.l1_off[wi + 1] - a.l1_off[wi];
+    nseg = nU;
+  } else {
+    nU = a.l1_off[wi + 1] - a.l1_off[wi];
+    nW = a.l2_off[wi + 1] - a.l2_off[wi];
+    nseg = nU + nW + (gB.w >= 2 ? 1 : 0);
+  }
+  int nt, tbase = 0;
+  T trad = T(0);
+  if (MODE == MODE_LEAF) {
+    int2 tr = a.box_tgt[B];
+    tbase = tr.x;
+    nt = tr.y - tr.x;
+  } else {
+    nt = a.n;
+    trad = T(MODE == MODE_P2M ? kRout : kRin);
+  }
+
+  for (int t0 = 0; t0 < nt; t0 += TCH * NCH) {
+    T tx[NCH], ty[NCH], tz[NCH];
+    double acc[NCH][RC];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      int t = t0 + c * TCH + ti;
+      tx[c] = ty[c] = tz[c] = T(0);
+      if (t < nt) {
+        if (MODE == MODE_LEAF) {
+          V p = a.tgt[tbase + t];
+          tx[c] = p.x;
+          ty[c] = p.y;
+          tz[c] = p.z;
+        } else {
+          double4 s = a.surf[t];
+          tx[c] = T(double(trad) * s.x);
+          ty[c] = T(double(trad) * s.y);
+          tz[c] = T(double(trad) * s.z);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RC; ++r) acc[c][r] = 0.0;
+    }
+    int nchunks = (min(nt - t0, TCH * NCH) + TCH - 1) / TCH;
+
+    for (int sw = 0; sw < nseg; sw += MAXSEG) {
+      const int nw = min(MAXSEG, nseg - sw);
+      __syncthreads();
+      if (tid < nw) {
+        const int si = sw + tid;
+        int kind, id, size;
+        double4 g;
+        if (MODE == MODE_P2M) {
+          int2 sr = a.box_src[B];
+          kind = SEG_POINTS;
+          id = sr.x;
+          size = sr.y - sr.x;
+          g = make_double4(0.0, 0.0, 0.0, 1.0);
+        } else if (si < nU) {
+          int A = a.l1_items[a.l1_off[wi] + si];
+          int2 sr = a.box_src[A];
+          kind = SEG_POINTS;
+          id = sr.x;
+          size = sr.y - sr.x;
+          g = frame(a.box_geo[A], gB);
+        } else if (si < nU + nW) {
+          int A = a.l2_items[a.l2_off[wi] + (si - nU)];
+          kind = SEG_UP_EQUIV;
+          id = A;
+          size = a.n;
+          g = frame(a.box_geo[A], gB);
+          g.w *= kRin;
+        } else {
+          kind = SEG_DN_EQUIV;
+          id = B;
+          size = a.n;
+          g = make_double4(0.0, 0.0, 0.0, kRout);
+        }
+        s_kind[tid] = kind;
+        s_id[tid] = id;
+        s_geo[tid] = g;
+        s_pre[tid + 1] = size;
+      }
+      if (tid == 0) s_pre[0] = 0;
+      __syncthreads();
+      for (int off = 1; off < nw; off <<= 1) {
+        int v = (tid < nw && tid >= off) ? s_pre[tid + 1 - off] : 0;
+        __syncthreads();
+        if (tid < nw) s_pre[tid + 1] += v;
+        __syncthreads();
+      }
+      const int total = s_pre[nw];
+
+      for (int b0 = 0; b0 < total; b0 += CAP) {
+        const int nb = min(CAP, total - b0);
+        for (int j = tid; j < nb; j += NT) {
+          const int gidx = b0 + j;
+          int lo = 0, hi = nw - 1;
+          while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= gidx) lo = mid;
+            else hi = mid - 1;
+          }
+          const int local = gidx - s_pre[lo];
+          const int kind = s_kind[lo];
+          const double4 g = s_geo[lo];
+          double px, py, pz;
+          if (kind == SEG_POINTS) {
+            const int64_t pi = int64_t(s_id[lo]) + local;
+            double4 p = a.src64[pi];
+            px = g.x + g.w * p.x;
+            py = g.y + g.w * p.y;
+            pz = g.z + g.w * p.z;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+              int rr = rhs0 + r;
+              s_q[r * CAP + j] = rr < a.n_rhs ? a.qs[int64_t(rr) * a.nsrc + pi] : T(0);
+            }
+          } else {
+            double4 s = a.surf[local];
+            px = g.x + g.w * s.x;
+            py = g.y + g.w * s.y;
+            pz = g.z + g.w * s.z;
+            const T* dens = kind == SEG_UP_EQUIV ? a.up_eq : a.dn_eq;
+            const int64_t col0 = int64_t(s_id[lo]) * a.n_rhs;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+              int rr = rhs0 + r;
+              s_q[r * CAP + j] = rr < a.n_rhs ? dens[(col0 + rr) * a.ld + local] : T(0);
+            }
+          }
+          V v;
+          v.x = T(px);
+          v.y = T(py);
+          v.z = T(pz);
+          v.w = T(0);
+          s_pos[j] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+          if (c < nchunks) {
+            T part[RC];
+#pragma unroll
+            for (int r = 0; r < RC; ++r) part[r] = T(0);
+            const T x = tx[c], y = ty[c], z = tz[c];
+            for (int j = sl; j < nb; j += SL) {
+              V s = s_pos[j];
+              T dx = x - s.x, dy = y - s.y, dz = z - s.z;
+              T ri = rinv(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+              for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
+            }
+#pragma unroll
+            for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // reduce the slices of each chunk and write
+    const double rB = a.box_r[B];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      if (c < nchunks) {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RC; ++r) s_red[(sl * TCH + ti) * RC + r] = acc[c][r];
+        __syncthreads();
+        if (sl == 0) {
+          const int t = t0 + c * TCH + ti;
+          if (t < nt) {
+#pragma unroll
+            for (int r = 0; r < RC; ++r) {
+              double sum = 0.0;
+              for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * TCH + ti) * RC + r];
+              const int rr = rhs0 + r;
+              if (rr < a.n_rhs) {
+                if (MODE == MODE_LEAF) {
+                  a.pot[int64_t(rr) * a.ntgt + tbase + t] = sum * (kInv4Pi / rB);
+                } else {
+                  T* o = a.out_col + (int64_t(B) * a.n_rhs + rr) * a.ld + t;
+                  if (MODE == MODE_P2M) *o = T(sum * kInv4Pi);
+                  else *o += T(sum * kInv4Pi);
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// --- gathered GEMM on the matrix cores ------------------------------------
+// out[col] (+)= sum_steps op[step] * in[src col] over the tiles of a Plan.
+// A block owns TC = 64 output columns and up to 160 rows (one row group);
+// wave w owns columns [16w, 16w+16) and 10 row blocks of 16, accumulated by
+// 16x16x4 MFMA (FP32 or FP64).  Operator k-chunks and gathered input columns
+// are staged through LDS.
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <class TA> struct Mfma;
+// Output layout of the 16x16x4 products: lane l, register v holds
+// D[row(l, v)][l % 16].  FP32 keeps four consecutive rows per lane, FP64
+// strides them by four.
+template <> struct Mfma<float> {
+  using acc = f32x4;
+  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  __device__ static inline acc step(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  using acc = f64x4;
+  __device__ static inline int row(int lane, int v) { return 4 * v + (lane >> 4); }
+  __device__ static inline acc step(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class TA, class TI, class TO>
+struct GemmArgs {
+  const TA* ops;
+  int64_t op_stride;
+  int ld, n_rhs, accumulate;
+  const TI* in;
+  TO* out;
+  const int32_t* tile_cols;
+  const int32_t* step_beg;
+  const int32_t* step_op;
+  const int32_t* step_src;
+  int TB;
+};
+
+constexpr int kTC = 64, kKC = 16, kRBMAX = 10, kROWS = kRBMAX * 16;
+
+template <class TA, class TI, class TO>
+__global__ __launch_bounds__(256) void gemm_plan_kernel(GemmArgs<TA, TI, TO> a) {
+  using M = Mfma<TA>;
+  __shared__ TA As[kROWS][kKC + 1];
+  __shared__ TA Bs[kTC][kKC + 1];
+  __shared__ int s_cols[kTC];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tile = blockIdx.x;
+  const int row0 = blockIdx.y * kROWS;
+  const int nrb = min(kRBMAX, (a.ld - row0) / 16);
+  typename M::acc acc[kRBMAX];
+#pragma unroll
+  for (int i = 0; i < kRBMAX; ++i)
+    for (int v = 0; v < 4; ++v) acc[i][v] = TA(0);
+
+  const int ncols = a.TB * a.n_rhs;
+  const int sb = a.step_beg[tile], se = a.step_beg[tile + 1];
+  for (int st = sb; st < se; ++st) {
+    const int64_t opoff = int64_t(a.step_op[st]) * a.op_stride;
+    __syncthreads();
+    if (tid < kTC) {
+      int c = -1;
+      if (tid < ncols) {
+        int b = tid / a.n_rhs, r = tid % a.n_rhs;
+        int src = a.step_src[int64_t(st) * a.TB + b];
+        if (src >= 0) c = src * a.n_rhs + r;
+      }
+      s_cols[tid] = c;
+    }
+    __syncthreads();
+    for (int k0 = 0; k0 < a.ld; k0 += kKC) {
+      for (int e = tid; e < kROWS * kKC; e += 256) {
+        int i = e / kKC, kk = e % kKC, row = row0 + i;
+        As[i][kk] = row < a.ld ? a.ops[opoff + int64_t(row) * a.ld + k0 + kk] : TA(0);
+      }
+      for (int e = tid; e < kTC * kKC; e += 256) {
+        int s = e / kKC, kk = e % kKC, c = s_cols[s];
+        Bs[s][kk] = c >= 0 ? TA(a.in[int64_t(c) * a.ld + k0 + kk]) : TA(0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kKC; kk += 4) {
+        const TA bv = Bs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int i = 0; i < kRBMAX; ++i)
+          if (i < nrb) acc[i] = M::step(As[i * 16 + (lane & 15)][kk + (lane >> 4)], bv, acc[i]);
+      }
+      __syncthreads();
+    }
+  }
+  const int s = wave * 16 + (lane & 15);
+  if (s < ncols) {
+    const int b = s / a.n_rhs, r = s % a.n_rhs;
+    const int box = a.tile_cols[int64_t(tile) * a.TB + b];
+    if (box >= 0) {
+      TO* o = a.out + (int64_t(box) * a.n_rhs + r) * a.ld;
+#pragma unroll
+      for (int i = 0; i < kRBMAX; ++i) {
+        if (i < nrb) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0 + i * 16 + M::row(lane, v);
+            TA val = acc[i][v];
+            if (a.accumulate) val += TA(o[row]);
+            o[row] = TO(val);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// pipeline
+// ------------------------------------------------------------------------
+
+template <class TA, class TI, class TO>
+static void run_gemm(const DevPlan& P, const TA* ops, int64_t op_stride, int ld, int n_rhs,
+                     const TI* in, TO* out, bool accumulate, hipStream_t s, PhaseScope& ps) {
+  if (P.ntile == 0) return;
+  if (P.TB * n_rhs > kTC) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
+  GemmArgs<TA, TI, TO> g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, in, out,
+                         P.tile_cols, P.step_beg, P.step_op, P.step_src, P.TB};
+  dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
+  hipLaunchKernelGGL((gemm_plan_kernel<TA, TI, TO>), grid, dim3(256), 0, s, g);
+  LAUNCHCHECK("gemm_plan_kernel");
+  ps.launches++;
+}
+
+template <class T, int MODE, int RC, int TCH>
+static void run_p2p(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
+  if (nwork == 0) return;
+  dim3 grid(nwork, (n_rhs + RC - 1) / RC);
+  hipLaunchKernelGGL((p2p_kernel<T, MODE, RC, TCH>), grid, dim3(256), 0, s, args);
+  LAUNCHCHECK("p2p_kernel");
+  ps.launches++;
+}
+
+template <class T, int MODE, int TCH>
+static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
+  if (n_rhs == 1) run_p2p<T, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
+  else run_p2p<T, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
+}
+
+template <class T, class TIO>
+static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* charges,
+                     void* const* potentials, int n_rhs, hipStream_t s) {
+  const int ld = F.ld;
+  const int64_t nn = int64_t(ld) * ld;
+  T* qs = static_cast<T*>(W.qs);
+  T* up_chk = static_cast<T*>(W.up_chk);
+  T* up_eq = static_cast<T*>(W.up_eq);
+  T* dn_chk = static_cast<T*>(W.dn_chk);
+  T* dn_eq = static_cast<T*>(W.dn_eq);
+  const T* m2m = nullptr;
+  const T* l2l = nullptr;
+  const T* m2l = nullptr;
+  if constexpr (sizeof(T) == 8) {
+    m2m = O.m2m64;
+    l2l = O.l2l64;
+    m2l = O.m2l64;
+  } else {
+    m2m = O.m2m32;
+    l2l = O.l2l32;
+    m2l = O.m2l32;
+  }
+
+  {
+    PhaseScope ps(PH_GATHER, s);
+    for (int k0 = 0; k0 < F.nprob; k0 += kMaxProb) {
+      int nk = std::min(kMaxProb, F.nprob - k0);
+      PtrPack pk{};
+      for (int k = 0; k < nk; ++k) pk.p[k] = charges[k0 + k];
+      dim3 grid(unsigned((F.max_src_per_prob + 255) / 256), nk);
+      hipLaunchKernelGGL((gather_kernel<TIO, T>), grid, dim3(256), 0, s, pk, k0, F.src_off,
+                         F.src_perm, n_rhs, F.nsrc, qs);
+      LAUNCHCHECK("gather_kernel");
+      ps.launches++;
+    }
+  }
+  P2PArgs<T> base{};
+  base.box_geo = F.box_geo;
+  base.box_r = F.box_r;
+  base.box_src = F.box_src;
+  base.box_tgt = F.box_tgt;
+  base.src64 = F.src64;
+  if constexpr (sizeof(T) == 8) base.tgt = F.tgt64;
+  else base.tgt = F.tgt32;
+  base.qs = qs;
+  base.nsrc = F.nsrc;
+  base.n_rhs = n_rhs;
+  base.surf = O.surf;
+  base.n = O.n;
+  base.ld = ld;
+  base.up_eq = up_eq;
+  base.dn_eq = dn_eq;
+  base.pot = W.pot;
+  base.ntgt = F.ntgt;
+  {
+    PhaseScope ps(PH_P2M, s);
+    P2PArgs<T> a = base;
+    a.work = F.p2m_boxes;
+    a.out_col = up_chk;
+    run_p2p_rc<T, MODE_P2M, 64>(a, F.n_p2m, n_rhs, s, ps);
+  }
+  for (int l = F.depth; l >= 2; --l) {
+    {
+      PhaseScope ps(PH_M2M, s);
+      run_gemm<T, T, T>(F.m2m[l], m2m, nn, ld, n_rhs, up_eq, up_chk, false, s, ps);
+    }
+    {
+      PhaseScope ps(PH_UC2E, s);
+      run_gemm<double, T, T>(F.uc2e[l], O.uc2e, 0, ld, n_rhs, up_chk, up_eq, false, s, ps);
+    }
+  }
+  {
+    PhaseScope ps(PH_P2L, s);
+    int64_t n16 = int64_t(W.col_bytes / 16);
+    hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, static_cast<uint4*>(W.dn_chk), n16);
+    LAUNCHCHECK("zero_kernel");
+    ps.launches++;
+    P2PArgs<T> a = base;
+    a.work = F.x_boxes;
+    a.l1_off = F.x_off;
+    a.l1_items = F.x_items;
+    a.out_col = dn_chk;
+    run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, s, ps);
+  }
+  {
+    PhaseScope ps(PH_M2L, s);
+    run_gemm<T, T, T>(F.m2l, m2l, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+  }
+  for (int l = 2; l <= F.depth; ++l) {
+    if (l >= 3) {
+      PhaseScope ps(PH_L2L, s);
+      run_gemm<T, T, T>(F.l2l[l], l2l, nn, ld, n_rhs, dn_eq, dn_chk, true, s, ps);
+    }
+    {
+      PhaseScope ps(PH_DC2E, s);
+      run_gemm<double, T, T>(F.dc2e[l], O.dc2e, 0, ld, n_rhs, dn_chk, dn_eq, false, s, ps);
+    }
+  }
+  {
+    PhaseScope ps(PH_LEAF, s);
+    P2PArgs<T> a = base;
+    a.work = F.leaf_boxes;
+    a.l1_off = F.u_off;
+    a.l1_items = F.u_items;
+    a.l2_off = F.w_off;
+    a.l2_items = F.w_items;
+    run_p2p_rc<T, MODE_LEAF, 32>(a, F.n_leaf, n_rhs, s, ps);
+  }
+  {
+    PhaseScope ps(PH_SCATTER, s);
+    for (int k0 = 0; k0 < F.nprob; k0 += kMaxProb) {
+      int nk = std::min(kMaxProb, F.nprob - k0);
+      PtrPack pk{};
+      for (int k = 0; k < nk; ++k) pk.p[k] = potentials[k0 + k];
+      dim3 grid(unsigned((F.max_tgt_per_prob + 255) / 256), nk);
+      hipLaunchKernelGGL((scatter_kernel<TIO>), grid, dim3(256), 0, s, pk, k0, F.tgt_off,
+                         F.tgt_perm, n_rhs, F.ntgt, W.pot);
+      LAUNCHCHECK("scatter_kernel");
+      ps.launches++;
+    }
+  }
+}
+
+void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const void* const* charges,
+                     void* const* potentials, int n_rhs, bool io_fp64, kifmm_precision prec,
+                     void* stream) {
+  const int dev = current_device();
+  if (!st.forest || st.device != dev) {
+    delete st.forest;
+    st.forest = nullptr;
+    st.forest = upload_forest(*st.host, hops.n);
+    st.device = dev;
+  }
+  if (prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5)
+    raise(KIFMM_EUNSUPPORTED, "evaluate: split-BF16 M2L is not available in this build");
+  const bool fp64 = prec == KIFMM_FP64;
+  DevOps* O = ops_for_device(oc, hops, dev, fp64);
+  DevForest& F = *st.forest;
+  if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
+  DevWork* W = work_for(F, fp64, n_rhs);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (fp64) {
+    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, s);
+    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, s);
+  } else {
+    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, s);
+    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, s);
+  }
+}
+
+void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out) {
+  if (!st.forest) raise(KIFMM_EINVAL, "debug_buffer: no evaluation has run on this tree");
+  DevForest& F = *st.forest;
+  auto it = F.work.find({fp64 ? 1 : 0, n_rhs});
+  if (it == F.work.end()) raise(KIFMM_EINVAL, "debug_buffer: no evaluation with this precision and n_rhs");
+  DevWork& W = *it->second;
+  HIPCHECK(hipDeviceSynchronize());
+  const size_t es = fp64 ? 8 : 4;
+  if (which == 4) {
+    size_t cnt = size_t(n_rhs) * F.ntgt;
+    if (n_out < int64_t(cnt)) raise(KIFMM_EINVAL, "debug_buffer: output too small");
+    HIPCHECK(hipMemcpy(out, W.pot, cnt * 8, hipMemcpyDeviceToHost));
+    return;
+  }
+  void* src = which == 0 ? W.up_chk : which == 1 ? W.up_eq : which == 2 ? W.dn_chk : which == 3 ? W.dn_eq : nullptr;
+  if (!src) raise(KIFMM_EINVAL, "debug_buffer: which must be 0..4");
+  const size_t cols = size_t(F.nbox) * n_rhs;
+  if (n_out < int64_t(cols * F.n)) raise(KIFMM_EINVAL, "debug_buffer: output too small");
+  std::vector<unsigned char> h(cols * F.ld * es);
+  HIPCHECK(hipMemcpy(h.data(), src, h.size(), hipMemcpyDeviceToHost));
+  for (size_t c = 0; c < cols; ++c)
+    for (int k = 0; k < F.n; ++k) {
+      size_t i = c * F.ld + k;
+      out[c * F.n + k] = fp64 ? reinterpret_cast<double*>(h.data())[i] : double(reinterpret_cast<float*>(h.data())[i]);
+    }
+}
+
+void evaluate_simple_host(EvalState& st, const HostOps& hops, OpsCache& oc, const double* q,
+                          int64_t nsrc, double* pot, int64_t ntgt) {
+  std::vector<void*> bufs;
+  struct Free {
+    std::vector<void*>& b;
+    ~Free() {
+      for (void* p : b) (void)hipFree(p);
+    }
+  } fr{bufs};
+  double* dq = dev_alloc<double>(bufs, size_t(nsrc));
+  double* dp = dev_alloc<double>(bufs, size_t(ntgt));
+  HIPCHECK(hipMemcpy(dq, q, size_t(nsrc) * 8, hipMemcpyHostToDevice));
+  const void* qa[1] = {dq};
+  void* pa[1] = {dp};
+  evaluate_forest(st, hops, oc, qa, pa, 1, true, KIFMM_FP32, nullptr);
+  HIPCHECK(hipStreamSynchronize(nullptr));
+  HIPCHECK(hipMemcpy(pot, dp, size_t(ntgt) * 8, hipMemcpyDeviceToHost));
+}
+
+}  // namespace kifmm

@@ -1,0 +1,256 @@
+// Forest assembly and gathered-GEMM tile plans.
+#include "forest.hpp"
+
+#include <algorithm>
+#include <array>
+#include <map>
+
+#include "common.hpp"
+
+namespace kifmm {
+namespace {
+
+// Groups `boxes` by key, keeps the given order inside a group, and cuts each
+// group into tiles of TB columns.
+template <class KeyF>
+std::vector<std::vector<int32_t>> group_tiles(const std::vector<int32_t>& boxes, int TB, KeyF key) {
+  std::map<int64_t, std::vector<int32_t>> groups;
+  for (int32_t b : boxes) groups[key(b)].push_back(b);
+  std::vector<std::vector<int32_t>> tiles;
+  for (auto& g : groups)
+    for (size_t i = 0; i < g.second.size(); i += TB)
+      tiles.emplace_back(g.second.begin() + i,
+                         g.second.begin() + std::min(g.second.size(), i + size_t(TB)));
+  return tiles;
+}
+
+// Appends one tile whose column j takes, at each step, the source given by
+// src(j, step) (or -1).
+void add_tile(Plan& P, const std::vector<int32_t>& cols, const std::vector<int32_t>& ops,
+              const std::vector<std::vector<int32_t>>& srcs) {
+  const int TB = P.TB;
+  for (int j = 0; j < TB; ++j) P.tile_cols.push_back(j < int(cols.size()) ? cols[j] : -1);
+  for (size_t s = 0; s < ops.size(); ++s) {
+    P.step_op.push_back(ops[s]);
+    for (int j = 0; j < TB; ++j) {
+      int32_t v = j < int(cols.size()) ? srcs[s][j] : -1;
+      P.step_src.push_back(v);
+      if (v >= 0) P.useful_pairs++;
+    }
+  }
+  P.step_beg.push_back(int32_t(P.step_op.size()));
+  P.ntile++;
+}
+
+Plan new_plan(int TB) {
+  Plan P;
+  P.TB = TB;
+  P.step_beg.push_back(0);
+  return P;
+}
+
+}  // namespace
+
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB) {
+  auto* Fp = new HostForest();
+  HostForest& F = *Fp;
+  F.nprob = n;
+  F.src_off.assign(n + 1, 0);
+  F.tgt_off.assign(n + 1, 0);
+  F.box_off.assign(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    F.src_off[k + 1] = F.src_off[k] + trees[k]->nsrc;
+    F.tgt_off[k + 1] = F.tgt_off[k] + trees[k]->ntgt;
+    F.box_off[k + 1] = F.box_off[k] + trees[k]->nbox;
+    F.depth = std::max(F.depth, trees[k]->depth);
+  }
+  F.nsrc = F.src_off[n];
+  F.ntgt = F.tgt_off[n];
+  F.nbox = F.box_off[n];
+  if (F.nsrc > (int64_t(1) << 31) - 1 || F.ntgt > (int64_t(1) << 31) - 1)
+    raise(KIFMM_EUNSUPPORTED, "forest: more than 2^31-1 points");
+  const int32_t NB = F.nbox;
+  F.box_geo.resize(4 * size_t(NB));
+  F.box_r.resize(NB);
+  F.box_src.resize(2 * size_t(NB));
+  F.box_tgt.resize(2 * size_t(NB));
+  F.box_parent.resize(NB);
+  F.box_octant.resize(NB);
+  F.box_leaf.resize(NB);
+  F.src_f64.resize(4 * size_t(F.nsrc));
+  F.tgt_f64.resize(4 * size_t(F.ntgt));
+  F.src_perm.resize(F.nsrc);
+  F.tgt_perm.resize(F.ntgt);
+
+  std::vector<int32_t> boxes_by_level_src, tmp;
+  std::vector<std::vector<int32_t>> lvl_boxes(F.depth + 1);
+  for (int k = 0; k < n; ++k) {
+    const HostTree& T = *trees[k];
+    const int32_t bo = F.box_off[k];
+    const int64_t so = F.src_off[k], to = F.tgt_off[k];
+    for (int32_t b = 0; b < T.nbox; ++b) {
+      int32_t g = bo + b;
+      for (int d = 0; d < 3; ++d) F.box_geo[4 * size_t(g) + d] = T.anchor[3 * b + d];
+      F.box_geo[4 * size_t(g) + 3] = T.level[b];
+      F.box_r[g] = T.halfwidth(T.level[b]);
+      F.box_src[2 * size_t(g)] = int32_t(so + T.sbeg[b]);
+      F.box_src[2 * size_t(g) + 1] = int32_t(so + T.send[b]);
+      F.box_tgt[2 * size_t(g)] = int32_t(to + T.tbeg[b]);
+      F.box_tgt[2 * size_t(g) + 1] = int32_t(to + T.tend[b]);
+      F.box_parent[g] = T.parent[b] < 0 ? -1 : bo + T.parent[b];
+      F.box_octant[g] = T.octant[b];
+      F.box_leaf[g] = T.leaf[b];
+      lvl_boxes[T.level[b]].push_back(g);
+      if (T.leaf[b]) {
+        double c[3], r = T.halfwidth(T.level[b]);
+        T.center(b, c);
+        for (int64_t i = T.sbeg[b]; i < T.send[b]; ++i)
+          for (int d = 0; d < 3; ++d) F.src_f64[4 * (so + i) + d] = (T.sxyz[3 * i + d] - c[d]) / r;
+        for (int64_t i = T.tbeg[b]; i < T.tend[b]; ++i)
+          for (int d = 0; d < 3; ++d) F.tgt_f64[4 * (to + i) + d] = (T.txyz[3 * i + d] - c[d]) / r;
+      }
+    }
+    for (int64_t i = 0; i < T.nsrc; ++i) F.src_perm[so + i] = int32_t(T.sperm[i]);
+    for (int64_t i = 0; i < T.ntgt; ++i) F.tgt_perm[to + i] = int32_t(T.tperm[i]);
+  }
+  F.src_f32.assign(F.src_f64.begin(), F.src_f64.end());
+  F.tgt_f32.assign(F.tgt_f64.begin(), F.tgt_f64.end());
+
+  auto nsrc_of = [&](int32_t g) { return F.box_src[2 * size_t(g) + 1] - F.box_src[2 * size_t(g)]; };
+  auto ntgt_of = [&](int32_t g) { return F.box_tgt[2 * size_t(g) + 1] - F.box_tgt[2 * size_t(g)]; };
+
+  // leaf work lists and the U, W, X lists in global ids
+  F.u_off.push_back(0);
+  F.w_off.push_back(0);
+  F.x_off.push_back(0);
+  for (int k = 0; k < n; ++k) {
+    const HostTree& T = *trees[k];
+    const int32_t bo = F.box_off[k];
+    for (int32_t b = 0; b < T.nbox; ++b) {
+      const int32_t g = bo + b;
+      if (T.leaf[b] && T.level[b] >= 2 && T.nsrc_of(b) > 0) F.p2m_boxes.push_back(g);
+      if (T.leaf[b] && T.ntgt_of(b) > 0) {
+        F.leaf_boxes.push_back(g);
+        for (int64_t e = T.off[LIST_U][b]; e < T.off[LIST_U][b + 1]; ++e) {
+          int32_t a = T.items[LIST_U][e];
+          F.u_items.push_back(bo + a);
+          F.p2p_interactions += T.ntgt_of(b) * T.nsrc_of(a);
+        }
+        for (int64_t e = T.off[LIST_W][b]; e < T.off[LIST_W][b + 1]; ++e)
+          F.w_items.push_back(bo + T.items[LIST_W][e]);
+        F.u_off.push_back(int32_t(F.u_items.size()));
+        F.w_off.push_back(int32_t(F.w_items.size()));
+      }
+      if (T.off[LIST_X][b + 1] > T.off[LIST_X][b] && T.ntgt_of(b) > 0) {
+        F.x_boxes.push_back(g);
+        for (int64_t e = T.off[LIST_X][b]; e < T.off[LIST_X][b + 1]; ++e)
+          F.x_items.push_back(bo + T.items[LIST_X][e]);
+        F.x_off.push_back(int32_t(F.x_items.size()));
+      }
+      F.n_v_pairs += T.off[LIST_V][b + 1] - T.off[LIST_V][b];
+    }
+  }
+  F.n_u_pairs = int64_t(F.u_items.size());
+  F.n_w_pairs = int64_t(F.w_items.size());
+  F.n_x_pairs = int64_t(F.x_items.size());
+
+  // plans
+  const int D = F.depth;
+  F.m2m.assign(D + 1, new_plan(TB));
+  F.uc2e.assign(D + 1, new_plan(TB));
+  F.l2l.assign(D + 1, new_plan(TB));
+  F.dc2e.assign(D + 1, new_plan(TB));
+  F.m2l = new_plan(TB);
+  for (int l = 2; l <= D; ++l) {
+    // M2M: non-leaf parents with sources; step o takes the child of octant o
+    std::vector<int32_t> parents, withsrc, withtgt;
+    for (int32_t g : lvl_boxes[l]) {
+      if (nsrc_of(g) > 0) withsrc.push_back(g);
+      if (ntgt_of(g) > 0) withtgt.push_back(g);
+      if (!F.box_leaf[g] && nsrc_of(g) > 0) parents.push_back(g);
+    }
+    if (!parents.empty()) {
+      // child of octant o of each parent, in a lookup by (parent, octant)
+      std::map<std::pair<int32_t, int>, int32_t> child;
+      for (int32_t g : lvl_boxes[l + 1 <= D ? l + 1 : l])
+        if (l + 1 <= D && nsrc_of(g) > 0) child[{F.box_parent[g], F.box_octant[g]}] = g;
+      for (auto& tile : group_tiles(parents, TB, [](int32_t) { return int64_t(0); })) {
+        std::vector<int32_t> opl;
+        std::vector<std::vector<int32_t>> srcs;
+        for (int o = 0; o < 8; ++o) {
+          std::vector<int32_t> s(tile.size(), -1);
+          bool any = false;
+          for (size_t j = 0; j < tile.size(); ++j) {
+            auto it = child.find({tile[j], o});
+            if (it != child.end()) {
+              s[j] = it->second;
+              any = true;
+            }
+          }
+          if (any) {
+            opl.push_back(o);
+            srcs.push_back(s);
+          }
+        }
+        add_tile(F.m2m[l], tile, opl, srcs);
+      }
+    }
+    for (auto& tile : group_tiles(withsrc, TB, [](int32_t) { return int64_t(0); }))
+      add_tile(F.uc2e[l], tile, {0}, {tile});
+    for (auto& tile : group_tiles(withtgt, TB, [](int32_t) { return int64_t(0); }))
+      add_tile(F.dc2e[l], tile, {0}, {tile});
+    if (l >= 3) {
+      for (auto& tile : group_tiles(withtgt, TB, [&](int32_t g) { return int64_t(F.box_octant[g]); })) {
+        std::vector<int32_t> par(tile.size());
+        for (size_t j = 0; j < tile.size(); ++j) par[j] = F.box_parent[tile[j]];
+        add_tile(F.l2l[l], tile, {F.box_octant[tile[0]]}, {par});
+      }
+    }
+  }
+  // M2L: targets grouped by (level, octant), steps = union of the tile's offsets
+  {
+    std::vector<int32_t> tg;
+    // V lists per global box
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> vl(NB);  // (op, source)
+    for (int k = 0; k < n; ++k) {
+      const HostTree& T = *trees[k];
+      const int32_t bo = F.box_off[k];
+      for (int32_t b = 0; b < T.nbox; ++b) {
+        if (T.ntgt_of(b) == 0 || T.off[LIST_V][b + 1] == T.off[LIST_V][b]) continue;
+        const int32_t g = bo + b;
+        tg.push_back(g);
+        for (int64_t e = T.off[LIST_V][b]; e < T.off[LIST_V][b + 1]; ++e) {
+          int32_t a = T.items[LIST_V][e];
+          int dx = T.anchor[3 * a] - T.anchor[3 * b];
+          int dy = T.anchor[3 * a + 1] - T.anchor[3 * b + 1];
+          int dz = T.anchor[3 * a + 2] - T.anchor[3 * b + 2];
+          int op = ops.m2l_index[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)];
+          if (op < 0) raise(KIFMM_EINVAL, "forest: V-list offset outside the M2L table");
+          vl[g].push_back({op, bo + a});
+        }
+      }
+    }
+    auto tiles = group_tiles(tg, TB, [&](int32_t g) {
+      return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g];
+    });
+    for (auto& tile : tiles) {
+      std::map<int32_t, std::vector<int32_t>> steps;
+      for (size_t j = 0; j < tile.size(); ++j)
+        for (auto& e : vl[tile[j]]) {
+          auto& s = steps[e.first];
+          if (s.empty()) s.assign(tile.size(), -1);
+          s[j] = e.second;
+        }
+      std::vector<int32_t> opl;
+      std::vector<std::vector<int32_t>> srcs;
+      for (auto& s : steps) {
+        opl.push_back(s.first);
+        srcs.push_back(s.second);
+      }
+      add_tile(F.m2l, tile, opl, srcs);
+    }
+  }
+  return Fp;
+}
+
+}  // namespace kifmm

@@ -1,0 +1,62 @@
+// A forest: one or more host trees merged into the flat arrays the device
+// kernels read, plus the tile plans of the gathered GEMMs (M2M, L2L, the
+// check-to-equivalent solves and M2L).
+//
+// Box "columns": every box b owns n_rhs columns of a density or check
+// potential buffer, column (b * n_rhs + r) of length ld (ld = n rounded up to
+// 16, padding rows zero).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "host_tree.hpp"
+#include "precompute.hpp"
+
+namespace kifmm {
+
+// out[tile_cols[t][j]] (+)= sum over the tile's steps s of
+//   op[step_op[s]] * in[step_src[s][j]]      (j < TB; -1 entries are skipped)
+struct Plan {
+  int32_t ntile = 0, TB = 0;
+  std::vector<int32_t> tile_cols;  // [ntile][TB]
+  std::vector<int32_t> step_beg;   // [ntile + 1]
+  std::vector<int32_t> step_op;    // [nstep]
+  std::vector<int32_t> step_src;   // [nstep][TB]
+  int64_t nstep() const { return int64_t(step_op.size()); }
+  int64_t useful_pairs = 0;        // (column, step) pairs with a source
+};
+
+struct HostForest {
+  int32_t nprob = 0, nbox = 0, depth = 0;
+  int64_t nsrc = 0, ntgt = 0;
+  std::vector<int64_t> src_off, tgt_off;  // per problem point ranges [nprob + 1]
+  std::vector<int32_t> box_off;           // per problem box ranges [nprob + 1]
+  // per box
+  std::vector<int32_t> box_geo;     // [nbox][4] anchor x, y, z, level
+  std::vector<double> box_r;        // [nbox] half-width
+  std::vector<int32_t> box_src;     // [nbox][2] global sorted source range
+  std::vector<int32_t> box_tgt;     // [nbox][2]
+  std::vector<int32_t> box_parent;  // global id or -1
+  std::vector<int32_t> box_octant, box_leaf;
+  // points, sorted, coordinates relative to their leaf: (x - c) / r, w = 0
+  std::vector<double> src_f64, tgt_f64;  // [n][4]
+  std::vector<float> src_f32, tgt_f32;   // [n][4]
+  std::vector<int32_t> src_perm, tgt_perm;  // sorted -> caller index (within problem)
+  // leaf work lists
+  std::vector<int32_t> p2m_boxes;   // leaves at level >= 2 holding sources
+  std::vector<int32_t> leaf_boxes;  // leaves holding targets
+  std::vector<int32_t> u_off, u_items, w_off, w_items;  // CSR over leaf_boxes
+  std::vector<int32_t> x_boxes, x_off, x_items;         // boxes with a non-empty X list
+  // per-level plans (index = level) and the all-level M2L plan
+  std::vector<Plan> m2m, uc2e, l2l, dc2e;
+  Plan m2l;
+  // statistics of the lists (for work counts)
+  int64_t n_u_pairs = 0, n_v_pairs = 0, n_w_pairs = 0, n_x_pairs = 0;
+  int64_t p2p_interactions = 0;  // sum over U pairs of n_tgt(B) * n_src(A)
+};
+
+// Builds the forest of `n` trees for operator set `ops` and plan width TB.
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB);
+
+}  // namespace kifmm

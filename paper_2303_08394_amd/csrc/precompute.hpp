@@ -1,0 +1,43 @@
+// Operator precomputation on the host in FP64 (section "Computational
+// structure of FMM operators": surfaces of n_e = 6(p-1)^2 + 2 points and
+// check-to-equivalent solves; section "Parallelization strategies for FMM
+// operators": M2M/L2L precomputed once and scaled per level).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace kifmm {
+
+constexpr double kRadiusInner = 1.05;  // upward equivalent / downward check
+constexpr double kRadiusOuter = 2.95;  // upward check / downward equivalent
+constexpr int kNumM2L = 316;           // offsets in {-3..3}^3 minus {-1..1}^3
+
+struct HostOps {
+  int p = 0, n = 0;
+  double rcond = 0;
+  std::vector<double> surf;  // [n][3] unit-cube surface points
+  // Reference operators (box half-width 1), row-major [rows][cols]:
+  //   uc2e, dc2e  [n][n]    scaled check potential -> density
+  //   m2m [8][n][n]         child density -> parent scaled check (parent r = 1)
+  //   l2l [8][n][n]         parent density -> child scaled check (child r = 1)
+  //   m2l [316][n][n]       source density -> target scaled check (same level)
+  // A "scaled" check potential is r times the check potential of a box of
+  // half-width r; with it every translation is independent of the level,
+  // because the kernel is homogeneous of degree -1 and pinv(K / r) = r pinv(K).
+  std::vector<double> uc2e, dc2e, m2m, l2l, m2l;
+  std::vector<int32_t> m2l_offset;  // [316][3] source anchor - target anchor
+  int32_t m2l_index[343];           // (dx+3)*49 + (dy+3)*7 + (dz+3) -> op, or -1
+};
+
+HostOps* build_host_ops(int p, double rcond);
+
+// One-sided Jacobi SVD of the square row-major matrix a [n][n]:
+// a = U diag(s) V^T; outputs U, V row-major [n][n], s descending.
+void jacobi_svd(const double* a, int n, std::vector<double>& U, std::vector<double>& s,
+                std::vector<double>& V);
+
+// Pseudo-inverse of a [n][n] from the SVD, dropping s_i < rcond * s_max.
+std::vector<double> pinv_truncated(const double* a, int n, double rcond, int* rank = nullptr);
+
+}  // namespace kifmm

@@ -1,0 +1,279 @@
+"""Python binding of libkifmm.so (include/kifmm.h): argument marshalling only.
+
+Every step of the evaluation runs in the HIP library; PyTorch supplies the
+device memory and the stream.  Importing this module never falls back to a
+CPU path: if the library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkifmm.so")
+
+FP64, FP32, M2L_BF16X3, M2L_BF16X5 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": M2L_BF16X3, "bf16x5": M2L_BF16X5}
+LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
+STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED"}
+
+
+class KifmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class TreeParams(C.Structure):
+    _fields_ = [("uniform_depth", C.c_int32), ("ncrit", C.c_int32), ("max_depth", C.c_int32),
+                ("balance", C.c_int32), ("root_center", C.c_double * 3),
+                ("root_halfwidth", C.c_double)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n_src", C.c_int64), ("n_tgt", C.c_int64), ("depth", C.c_int32),
+                ("n_boxes", C.c_int32), ("n_leaves", C.c_int32), ("reserved", C.c_int32),
+                ("n_u", C.c_int64), ("n_v", C.c_int64), ("n_w", C.c_int64), ("n_x", C.c_int64),
+                ("root_center", C.c_double * 3), ("root_halfwidth", C.c_double)]
+
+
+_lib = None
+EXPORTED = [
+    "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
+    "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_precompute_operators",
+    "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_batch",
+    "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
+    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
+]
+
+
+def lib():
+    """Loads libkifmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2303_08394_amd.build` (no CPU fallback exists)")
+    L = C.CDLL(LIB_PATH)
+    P, D, I32, I64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
+    L.kifmm_build_tree.argtypes = [D, I64, D, I64, C.POINTER(TreeParams), C.POINTER(P)]
+    L.kifmm_tree_get_info.argtypes = [P, C.POINTER(TreeInfo)]
+    L.kifmm_tree_export_boxes.argtypes = [P, P, P, P, P, P, P]
+    L.kifmm_tree_export_list.argtypes = [P, I32, P, P]
+    L.kifmm_tree_export_perm.argtypes = [P, P, P]
+    L.kifmm_precompute_operators.argtypes = [I32, C.c_double, C.POINTER(P)]
+    L.kifmm_ops_export.argtypes = [P, I32, D, I64]
+    L.kifmm_ops_n.argtypes = [P]
+    L.kifmm_ops_n.restype = I32
+    L.kifmm_evaluate.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
+    L.kifmm_evaluate_batch.argtypes = [I32, C.POINTER(P), P, C.POINTER(P), C.POINTER(P), I32,
+                                       C.c_int, P]
+    L.kifmm_evaluate_simple.argtypes = [D, D, I64, D, I64, I32, D]
+    L.kifmm_set_profiling.argtypes = [I32]
+    L.kifmm_n_phases.restype = I32
+    L.kifmm_phase_name.argtypes = [I32]
+    L.kifmm_phase_name.restype = C.c_char_p
+    L.kifmm_get_phase_times.argtypes = [D, C.POINTER(I64)]
+    L.kifmm_debug_buffer.argtypes = [P, I32, I32, I32, D, I64]
+    L.kifmm_tree_destroy.argtypes = [P]
+    L.kifmm_tree_destroy.restype = None
+    L.kifmm_ops_destroy.argtypes = [P]
+    L.kifmm_ops_destroy.restype = None
+    L.kifmm_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("kifmm_ops_n", "kifmm_n_phases", "kifmm_phase_name", "kifmm_last_error",
+                        "kifmm_tree_destroy", "kifmm_ops_destroy"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise KifmmError(st, lib().kifmm_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _vptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class Tree:
+    """Octree + interaction lists built by the library (host)."""
+
+    def __init__(self, src, tgt=None, *, uniform_depth: int = -1, ncrit: int = 64,
+                 max_depth: int = 12, balance: bool = True, center=None, halfwidth: float = 0.0):
+        L = lib()
+        self.src = np.ascontiguousarray(src, dtype=np.float64)
+        self.tgt = self.src if tgt is None else np.ascontiguousarray(tgt, dtype=np.float64)
+        prm = TreeParams()
+        prm.uniform_depth = uniform_depth
+        prm.ncrit = ncrit
+        prm.max_depth = max_depth
+        prm.balance = 1 if balance else 0
+        if halfwidth and halfwidth > 0:
+            prm.root_center[:] = [float(v) for v in center]
+            prm.root_halfwidth = float(halfwidth)
+        h = C.c_void_p()
+        _check(L.kifmm_build_tree(_dptr(self.src), len(self.src), _dptr(self.tgt), len(self.tgt),
+                                  C.byref(prm), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> TreeInfo:
+        inf = TreeInfo()
+        _check(lib().kifmm_tree_get_info(self._h, C.byref(inf)))
+        return inf
+
+    def boxes(self) -> dict:
+        nb = self.info().n_boxes
+        out = dict(level=np.zeros(nb, np.int32), anchor=np.zeros((nb, 3), np.int32),
+                   parent=np.zeros(nb, np.int32), is_leaf=np.zeros(nb, np.int32),
+                   src_range=np.zeros((nb, 2), np.int64), tgt_range=np.zeros((nb, 2), np.int64))
+        _check(lib().kifmm_tree_export_boxes(self._h, *[_vptr(out[k]) for k in
+                                                       ("level", "anchor", "parent", "is_leaf",
+                                                        "src_range", "tgt_range")]))
+        return out
+
+    def list(self, which: int):
+        nb = self.info().n_boxes
+        off = np.zeros(nb + 1, np.int64)
+        _check(lib().kifmm_tree_export_list(self._h, which, _vptr(off), None))
+        items = np.zeros(max(int(off[-1]), 1), np.int32)
+        _check(lib().kifmm_tree_export_list(self._h, which, _vptr(off), _vptr(items)))
+        return off, items[:int(off[-1])]
+
+    def perm(self):
+        inf = self.info()
+        s, t = np.zeros(inf.n_src, np.int64), np.zeros(inf.n_tgt, np.int64)
+        _check(lib().kifmm_tree_export_perm(self._h, _vptr(s), _vptr(t)))
+        return s, t
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kifmm_tree_destroy(h)
+            self._h = None
+
+
+class Operators:
+    """Operator tables of order p (host FP64; uploaded on first use)."""
+
+    def __init__(self, p: int, rcond: float = 1e-9):
+        h = C.c_void_p()
+        _check(lib().kifmm_precompute_operators(p, rcond, C.byref(h)))
+        self._h = h
+        self.p = p
+        self.rcond = rcond
+        self.n = lib().kifmm_ops_n(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self, which: int) -> np.ndarray:
+        n = self.n
+        shapes = {0: (n, 3), 1: (n, n), 2: (n, n), 3: (8, n, n), 4: (8, n, n),
+                  5: (316, n, n), 6: (316, 3)}
+        out = np.zeros(shapes[which])
+        _check(lib().kifmm_ops_export(self._h, which, _dptr(out), out.size))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.kifmm_ops_destroy(h)
+            self._h = None
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def evaluate(tree: Tree, ops: Operators, charges, precision="fp32", out=None, stream=None):
+    """Potentials at the tree's targets for device charges [n_rhs][n_src] (or [n_src]).
+
+    charges: torch CUDA tensor, float64 or float32 (the output takes its dtype).
+    Runs asynchronously on `stream` (default: torch's current stream)."""
+    import torch
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if not charges.is_cuda:
+        raise ValueError("charges must be a CUDA (HIP) tensor")
+    one = charges.dim() == 1
+    q = charges.reshape(1, -1) if one else charges
+    q = q.contiguous()
+    if q.dtype not in (torch.float64, torch.float32):
+        raise ValueError("charges must be float64 or float32")
+    inf = tree.info()
+    if q.shape[1] != inf.n_src:
+        raise ValueError(f"charges have {q.shape[1]} columns, the tree {inf.n_src} sources")
+    n_rhs = q.shape[0]
+    if out is None:
+        out = torch.empty((n_rhs, inf.n_tgt), dtype=q.dtype, device=q.device)
+    _check(lib().kifmm_evaluate(tree.handle, ops.handle, C.c_void_p(q.data_ptr()), n_rhs,
+                                C.c_void_p(out.data_ptr()), 1 if q.dtype == torch.float64 else 0,
+                                prec, _stream_ptr(stream)))
+    return out[0] if one else out
+
+
+def evaluate_batch(trees, ops: Operators, charges, precision="fp32", outs=None, stream=None):
+    """One pass over several independent problems (one charge vector each)."""
+    import torch
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    n = len(trees)
+    qs = [c.contiguous() for c in charges]
+    dt = qs[0].dtype
+    if outs is None:
+        outs = [torch.empty(t.info().n_tgt, dtype=dt, device=qs[0].device) for t in trees]
+    th = (C.c_void_p * n)(*[t.handle.value for t in trees])
+    qp = (C.c_void_p * n)(*[q.data_ptr() for q in qs])
+    op = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+    _check(lib().kifmm_evaluate_batch(n, th, ops.handle, qp, op,
+                                      1 if dt == torch.float64 else 0, prec, _stream_ptr(stream)))
+    return outs
+
+
+def debug_buffer(tree: Tree, which: int, n: int, fp64: bool, n_rhs: int = 1) -> np.ndarray:
+    """Intermediate buffer of the last evaluate on `tree` (see kifmm_debug_buffer):
+    which 0..3 -> [n_boxes][n_rhs][n], 4 -> [n_rhs][n_tgt]."""
+    inf = tree.info()
+    shape = (n_rhs, inf.n_tgt) if which == 4 else (inf.n_boxes, n_rhs, n)
+    out = np.zeros(shape)
+    _check(lib().kifmm_debug_buffer(tree.handle, which, 1 if fp64 else 0, n_rhs, _dptr(out), out.size))
+    return out
+
+
+def evaluate_simple(src, q, tgt, p: int) -> np.ndarray:
+    """Host arrays in, host FP64 potentials out (adaptive tree, FP32 evaluation)."""
+    src = np.ascontiguousarray(src, np.float64)
+    tgt = np.ascontiguousarray(tgt, np.float64)
+    q = np.ascontiguousarray(q, np.float64)
+    pot = np.zeros(len(tgt))
+    _check(lib().kifmm_evaluate_simple(_dptr(src), _dptr(q), len(src), _dptr(tgt), len(tgt), p,
+                                       _dptr(pot)))
+    return pot
+
+
+def set_profiling(on: bool):
+    _check(lib().kifmm_set_profiling(1 if on else 0))
+
+
+def phase_times() -> dict:
+    """{phase: (ms, launches)} accumulated since the last call (synchronises)."""
+    L = lib()
+    n = L.kifmm_n_phases()
+    ms = np.zeros(n)
+    la = np.zeros(n, np.int64)
+    _check(L.kifmm_get_phase_times(_dptr(ms), la.ctypes.data_as(C.POINTER(C.c_int64))))
+    return {L.kifmm_phase_name(i).decode(): (float(ms[i]), int(la[i])) for i in range(n)}

@@ -1,0 +1,174 @@
+"""Host-side checks of the C ABI (no GPU): symbols, error paths, the C++ tree
+and lists against the oracle's independent tree, and the FP64 precompute."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import kifmm as OK
+from oracle.direct import kernel_matrix
+from oracle.octree import Octree
+from oracle.surface import surface_grid
+from paper_2303_08394_amd import inputs as I
+from paper_2303_08394_amd import kifmm as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CUBE = dict(center=(0.5, 0.5, 0.5), halfwidth=0.5)
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "kifmm.h")).read()
+    declared = set(re.findall(r"\b(kifmm_\w+)\s*\(", hdr))
+    assert len(declared) >= 18
+    L = K.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(K.EXPORTED)
+
+
+def _tree_pair(x, tgt=None, **kw):
+    tgt = x if tgt is None else tgt
+    ot = Octree(x, tgt, **kw)
+    ct = K.Tree(x, tgt, **kw)
+    return ot, ct
+
+
+def _compare_trees(ot, ct):
+    cb = ct.boxes()
+    inf = ct.info()
+    assert inf.n_boxes == len(ot.level)
+    np.testing.assert_allclose(inf.root_center[:], ot.c0, rtol=0, atol=0)
+    assert inf.root_halfwidth == ot.r0
+    key = {(int(cb["level"][b]),) + tuple(int(v) for v in cb["anchor"][b]): b for b in range(inf.n_boxes)}
+    o2c = {}
+    sperm, tperm = ct.perm()
+    for ob in range(len(ot.level)):
+        k = (ot.level[ob],) + ot.anchor[ob]
+        assert k in key, k
+        cbx = key[k]
+        o2c[ob] = cbx
+        assert bool(cb["is_leaf"][cbx]) == ot.is_leaf(ob)
+        s0, s1 = cb["src_range"][cbx]
+        t0, t1 = cb["tgt_range"][cbx]
+        assert sorted(sperm[s0:s1].tolist()) == sorted(ot.srcs[ob].tolist())
+        assert sorted(tperm[t0:t1].tolist()) == sorted(ot.tgts[ob].tolist())
+    nsrc = {b: len(ot.srcs[b]) for b in range(len(ot.level))}
+    for which, fn in ((K.LIST_U, ot.U), (K.LIST_V, ot.V), (K.LIST_W, ot.W), (K.LIST_X, ot.X)):
+        off, items = ct.list(which)
+        for ob in range(len(ot.level)):
+            if len(ot.tgts[ob]) == 0:
+                continue
+            want = sorted(o2c[a] for a in fn(ob) if nsrc[a] > 0)
+            c = o2c[ob]
+            got = sorted(items[off[c]:off[c + 1]].tolist())
+            assert got == want, (which, ob)
+    return o2c
+
+
+def test_uniform_tree_matches_oracle():
+    x, _ = I.uniform_cube(5000, seed=1)
+    ot, ct = _tree_pair(x, uniform_depth=3, **CUBE)
+    _compare_trees(ot, ct)
+    assert ct.info().n_v == 56448 and ct.info().n_u == 10648
+
+
+@pytest.mark.parametrize("case", ["sphere", "clustered", "separate", "unbalanced", "root_from_data"])
+def test_adaptive_tree_matches_oracle(case):
+    if case == "sphere":
+        x, _ = I.sphere_surface(6000, seed=2)
+        ot, ct = _tree_pair(x, ncrit=20, max_depth=9)
+    elif case == "clustered":
+        x, _ = I.clustered(6000, seed=3)
+        ot, ct = _tree_pair(x, ncrit=24, max_depth=9, **CUBE)
+    elif case == "separate":
+        x, _ = I.clustered(3000, seed=4)
+        t = np.random.default_rng(4).random((2000, 3))
+        ot, ct = _tree_pair(x, t, ncrit=16, max_depth=8, **CUBE)
+    elif case == "unbalanced":
+        x, _ = I.clustered(3000, seed=5, sigma=0.03)
+        ot, ct = _tree_pair(x, ncrit=16, max_depth=9, balance=False, **CUBE)
+    else:
+        x, _ = I.sphere_surface(3000, seed=6)
+        ot, ct = _tree_pair(x + 3.0, ncrit=30, max_depth=8)
+    _compare_trees(ot, ct)
+    inf = ct.info()
+    if case != "unbalanced":
+        assert inf.n_w > 0 and inf.n_x > 0
+
+
+def test_points_on_faces_and_duplicates():
+    # points exactly on internal faces, on the root's upper face, and repeated
+    g = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    x = np.array([(a, b, c) for a in g for b in g for c in g])
+    x = np.vstack([x, x[:10]])
+    ot, ct = _tree_pair(x, ncrit=4, max_depth=5, **CUBE)
+    _compare_trees(ot, ct)
+
+
+def test_jacobi_svd_pinv_matches_library():
+    s = surface_grid(6)
+    for p in (2, 4, 6):
+        ops = K.Operators(p)
+        s = surface_grid(p)
+        ref_u = OK.pinv_truncated(kernel_matrix(2.95 * s, 1.05 * s), 1e-9)
+        ref_d = OK.pinv_truncated(kernel_matrix(1.05 * s, 2.95 * s), 1e-9)
+        # conditioning 1e9 at p=6 makes two correct pinvs differ by ~1e-8
+        tol = {2: 1e-13, 4: 1e-10, 6: 1e-7}[p]
+        assert np.linalg.norm(ops.export(1) - ref_u) / np.linalg.norm(ref_u) < tol
+        assert np.linalg.norm(ops.export(2) - ref_d) / np.linalg.norm(ref_d) < tol
+        np.testing.assert_allclose(ops.export(0), s, rtol=0, atol=1e-15)
+
+
+def test_translation_tables_match_oracle():
+    ops = K.Operators(4)
+    one = Octree(np.zeros((1, 3)), np.zeros((1, 3)), uniform_depth=0, center=(0, 0, 0), halfwidth=1.0)
+    two = Octree(np.zeros((1, 3)), np.zeros((1, 3)), uniform_depth=0, center=(0, 0, 0), halfwidth=2.0)
+    o1, o2 = OK.KIFMM(one, 4), OK.KIFMM(two, 4)
+    m2m, l2l, m2l, offs = ops.export(3), ops.export(4), ops.export(5), ops.export(6)
+    for o in range(8):
+        oc = ((o >> 2) & 1, (o >> 1) & 1, o & 1)
+        np.testing.assert_allclose(m2m[o], o1.m2m(1, oc), rtol=1e-13)
+        np.testing.assert_allclose(l2l[o], o2.l2l(1, oc), rtol=1e-13)
+    assert len({tuple(v) for v in offs.astype(int)}) == 316
+    for k in (0, 57, 315):
+        np.testing.assert_allclose(m2l[k], o1.m2l(0, tuple(offs[k].astype(int))), rtol=1e-13)
+
+
+def test_error_paths():
+    x = np.random.default_rng(0).random((10, 3))
+    with pytest.raises(K.KifmmError, match="EINVAL"):
+        K.Operators(1)
+    with pytest.raises(K.KifmmError, match="EINVAL"):
+        K.Operators(17)
+    with pytest.raises(K.KifmmError, match="EINVAL"):
+        K.Operators(6, rcond=0.0)
+    with pytest.raises(K.KifmmError, match="EINVAL"):
+        K.Tree(np.zeros((0, 3)))
+    bad = x.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(K.KifmmError, match="non-finite"):
+        K.Tree(bad)
+    bad[3, 1] = np.inf
+    with pytest.raises(K.KifmmError, match="non-finite"):
+        K.Tree(x, bad)
+    with pytest.raises(K.KifmmError, match="ncrit"):
+        K.Tree(x, ncrit=0)
+    with pytest.raises(K.KifmmError, match="max_depth"):
+        K.Tree(x, max_depth=21)
+    with pytest.raises(K.KifmmError, match="uniform_depth"):
+        K.Tree(x, uniform_depth=21)
+    L = K.lib()
+    import ctypes as C
+    h = C.c_void_p()
+    assert L.kifmm_build_tree(None, 10, None, 10, None, C.byref(h)) == 1
+    t = K.Tree(x)
+    ops = K.Operators(3)
+    # evaluate argument errors are caught before any device work
+    assert L.kifmm_evaluate(t.handle, ops.handle, None, 1, None, 1, 1, None) == 1
+    assert b"null" in L.kifmm_last_error()
+    assert L.kifmm_evaluate(t.handle, ops.handle, C.c_void_p(8), 0, C.c_void_p(8), 1, 1, None) == 1
+    assert L.kifmm_evaluate(None, ops.handle, C.c_void_p(8), 1, C.c_void_p(8), 1, 1, None) == 1
+    assert L.kifmm_evaluate(t.handle, ops.handle, C.c_void_p(8), 1, C.c_void_p(8), 1, 9, None) == 1
+    assert L.kifmm_evaluate(t.handle, ops.handle, C.c_void_p(8), 65, C.c_void_p(8), 1, 1, None) == 4
+    assert L.kifmm_tree_export_list(t.handle, 7, None, None) == 1
