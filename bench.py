@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12   # dense FP32 matrix FLOP/s
 PEAK_FP64_MFMA = 78.6e12
+PEAK_BF16_MFMA = 2.5e15     # dense BF16 matrix FLOP/s
 PEAK_HBM = 8.0e12
 # The particle kernels are bound by plain FP32 VALU issue: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s.  One pair interaction issues
@@ -79,6 +80,7 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-sample", type=int, default=200)
+    ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build evaluates on one GPU; --gpus {args.gpus} is not supported "
@@ -91,6 +93,8 @@ def main():
     from paper_2303_08394_amd import inputs as I
     from paper_2303_08394_amd import kifmm as K
 
+    if args.m2l_tile:
+        K.set_tuning("m2l_tile_cols", args.m2l_tile)
     prob = _workload(args)
     t0 = time.perf_counter()
     tree = K.Tree(prob.points, uniform_depth=prob.uniform_depth, ncrit=prob.ncrit,
@@ -157,10 +161,15 @@ def main():
         int(sum(nt[b] * (woff[b + 1] - woff[b]) for b in leaves)) * pn
     leaf_pairs = near_pairs + far_pairs
     if dom == "m2l":
-        roof = {"kernel": "gemm_plan_kernel (M2L)", "bound": "mfma",
+        # algorithmic flops (one product per V-list pair), against the peak of
+        # the instruction the path issues; split-BF16 issues 3 (5) products
+        peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
+                "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA}[args.precision]
+        issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5}[args.precision]
+        roof = {"kernel": "gemm_kernel (M2L)", "bound": "mfma",
                 "achieved": flops_m2l / (ms["m2l"] * 1e-3) / 1e12,
-                "peak": (PEAK_FP64_MFMA if args.precision == "fp64" else PEAK_FP32_MFMA) / 1e12,
-                "unit": "TFLOP/s"}
+                "peak": peak / 1e12, "unit": "TFLOP/s",
+                "issued_frac": issued * flops_m2l / (ms["m2l"] * 1e-3) / peak}
     else:
         roof = {"kernel": f"{dom}", "bound": "alu",
                 "achieved": leaf_pairs / (ms["leaf"] * 1e-3) / 1e12,

@@ -185,6 +185,13 @@ kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches);
 kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t fp64,
                                 int32_t n_rhs, double* out, int64_t n_out);
 
+/* Process-wide tuning knobs of the evaluation kernels, applied when an
+ * evaluation next builds its device plans (a change rebuilds them).
+ *   "m2l_tile_cols": output columns (box x right-hand side) per M2L block,
+ *                    64 (default) or 128.
+ * EINVAL for an unknown key or value. */
+kifmm_status kifmm_set_tuning(const char* key, int32_t value);
+
 void kifmm_tree_destroy(kifmm_tree* tree);
 void kifmm_ops_destroy(kifmm_ops* ops);
 

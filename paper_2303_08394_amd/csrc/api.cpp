@@ -1,6 +1,7 @@
 // The C ABI (include/kifmm.h): argument checks, handle ownership, caching of
 // device state, and translation of internal errors into status codes.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -57,6 +58,10 @@ static void purge_batches(const kifmm_tree* t, const kifmm_ops* o) {
 }
 
 static int plan_width(int n_rhs) { return std::max(1, 64 / n_rhs); }
+
+// tuning (see kifmm_set_tuning)
+static std::atomic<int> g_m2l_tile_cols{64};
+static int m2l_plan_width(int n_rhs) { return std::max(1, g_m2l_tile_cols.load() / n_rhs); }
 
 template <class F>
 static kifmm_status guard(F&& f) {
@@ -201,11 +206,12 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
     check_eval_args(tree, ops, n_rhs, precision);
     if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate: null charges or potentials");
     auto* t = const_cast<kifmm_tree*>(tree);
-    const int TB = plan_width(n_rhs);
-    if (!t->state || t->state_n != ops->host->n || t->state->host->m2l.TB != TB) {
+    const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
+    if (!t->state || t->state_n != ops->host->n || t->state->host->dc2e.back().TB != TB ||
+        t->state->host->m2l.TB != TBm) {
       t->state.reset(new EvalState());
       const HostTree* one = t->host.get();
-      t->state->host.reset(build_forest(&one, 1, *ops->host, TB));
+      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm));
       t->state_n = ops->host->n;
     }
     const void* q[1] = {charges};
@@ -231,11 +237,12 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
     {
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto& slot = g_batches[key];
+      if (slot && slot->host->m2l.TB != m2l_plan_width(1)) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);
         for (int k = 0; k < n_prob; ++k) hts[k] = trees[k]->host.get();
         auto s = std::make_unique<EvalState>();
-        s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1)));
+        s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1)));
         slot = std::move(s);
       }
       st = slot.get();
@@ -260,7 +267,7 @@ kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n
       if (!std::isfinite(q[i])) raise(KIFMM_EINVAL, "evaluate_simple: non-finite charge");
     EvalState st;
     const HostTree* one = ht.get();
-    st.host.reset(build_forest(&one, 1, *ho, plan_width(1)));
+    st.host.reset(build_forest(&one, 1, *ho, plan_width(1), m2l_plan_width(1)));
     OpsCache oc;
     evaluate_simple_host(st, *ho, oc, q, n_src, pot, n_tgt);
   });
@@ -285,6 +292,16 @@ void kifmm_ops_destroy(kifmm_ops* ops) {
   if (!ops) return;
   purge_batches(nullptr, ops);
   delete ops;
+}
+
+kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
+  if (!key) return fail(KIFMM_EINVAL, "set_tuning: null key");
+  if (std::strcmp(key, "m2l_tile_cols") == 0) {
+    if (value != 64 && value != 128) return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64 or 128");
+    g_m2l_tile_cols = value;
+    return KIFMM_OK;
+  }
+  return fail(KIFMM_EINVAL, std::string("set_tuning: unknown key ") + key);
 }
 
 kifmm_status kifmm_set_profiling(int32_t enable) {

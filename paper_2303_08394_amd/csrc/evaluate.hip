@@ -49,6 +49,7 @@ struct DevOps {
   double *uc2e = nullptr, *dc2e = nullptr;               // [ld][ld]
   float *m2m32 = nullptr, *l2l32 = nullptr, *m2l32 = nullptr;  // [k][ld][ld]
   double *m2m64 = nullptr, *l2l64 = nullptr, *m2l64 = nullptr;
+  uint16_t *m2l_bh = nullptr, *m2l_bl = nullptr;         // BF16 high/low parts of M2L
   double4* surf = nullptr;                               // [n] unit-cube surface
   std::vector<void*> allocs;
   ~DevOps() {
@@ -142,7 +143,9 @@ static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P) {
   return d;
 }
 
-static int round16(int n) { return (n + 15) / 16 * 16; }
+// Leading dimension of density columns and operators: n rounded up to the
+// GEMM k-chunk (32), padding rows and columns zero.
+static int round32(int n) { return (n + 31) / 32 * 32; }
 
 static DevForest* upload_forest(const HostForest& F, int n) {
   auto* D = new DevForest();
@@ -153,7 +156,7 @@ static DevForest* upload_forest(const HostForest& F, int n) {
     D->nsrc = F.nsrc;
     D->ntgt = F.ntgt;
     D->n = n;
-    D->ld = round16(n);
+    D->ld = round32(n);
     auto& A = D->allocs;
     D->box_geo = dev_upload<int4>(A, F.box_geo);
     D->box_r = dev_upload<double>(A, F.box_r);
@@ -205,12 +208,26 @@ static std::vector<T> pad_table(const std::vector<double>& src, int k, int n, in
   return out;
 }
 
-static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64) {
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+static uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+static double bf16_value(uint16_t b) {
+  uint32_t u = uint32_t(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64, bool bf16) {
   DevOps*& O = oc.per_device[dev];
   if (!O) {
     O = new DevOps();
     O->n = H.n;
-    O->ld = round16(H.n);
+    O->ld = round32(H.n);
     O->uc2e = dev_upload<double>(O->allocs, pad_table<double>(H.uc2e, 1, H.n, O->ld));
     O->dc2e = dev_upload<double>(O->allocs, pad_table<double>(H.dc2e, 1, H.n, O->ld));
     std::vector<double> s4(4 * size_t(H.n), 0.0);
@@ -222,6 +239,16 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64
     O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8, H.n, O->ld));
     O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8, H.n, O->ld));
     O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
+  }
+  if (bf16 && !O->m2l_bh) {
+    std::vector<double> pad = pad_table<double>(H.m2l, kNumM2L, H.n, O->ld);
+    std::vector<uint16_t> hi(pad.size()), lo(pad.size());
+    for (size_t i = 0; i < pad.size(); ++i) {
+      hi[i] = bf16_bits(float(pad[i]));
+      lo[i] = bf16_bits(float(pad[i] - bf16_value(hi[i])));
+    }
+    O->m2l_bh = dev_upload<uint16_t>(O->allocs, hi);
+    O->m2l_bl = dev_upload<uint16_t>(O->allocs, lo);
   }
   if (!fp64 && !O->m2l32) {
     O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8, H.n, O->ld));
@@ -656,114 +683,312 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 
 // --- gathered GEMM on the matrix cores ------------------------------------
 // out[col] (+)= sum_steps op[step] * in[src col] over the tiles of a Plan.
-// A block owns TC = 64 output columns and up to 160 rows (one row group);
-// wave w owns columns [16w, 16w+16) and 10 row blocks of 16, accumulated by
-// 16x16x4 MFMA (FP32 or FP64).  Operator k-chunks and gathered input columns
-// are staged through LDS.
+//
+// A block (4 waves) owns TC = 64*CB output columns and one group of up to 160
+// rows; wave w owns CB column blocks of 16 and 10 row blocks of 16.  The k
+// dimension advances in chunks of KC: lane group g = lane/16 always carries
+// the KC/4 consecutive k values [g*KC/4, (g+1)*KC/4) of a chunk, for both
+// operands, so each fragment is one or two 128-bit LDS reads.  That is a
+// valid assignment of k to the MFMA's k slots because A and B use the same
+// one.  Operator and gathered-column chunks are double-buffered in LDS: the
+// next chunk's global loads are in flight while the current one feeds the
+// matrix cores, with one barrier per chunk.
+//
+// Modes: FP32 (16x16x4 f32), FP64 (16x16x4 f64), and split BF16 on the
+// 16x16x32 bf16 instruction with FP32 accumulation: BF3 = A_h x_h + A_h x_l
+// + A_l x_h, BF5 additionally splits x three ways and adds A_l x_m + A_h x_l.
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-template <class TA> struct Mfma;
-// Output layout of the 16x16x4 products: lane l, register v holds
-// D[row(l, v)][l % 16].  FP32 keeps four consecutive rows per lane, FP64
-// strides them by four.
-template <> struct Mfma<float> {
+enum { GM_F32 = 0, GM_F64 = 1, GM_BF3 = 2, GM_BF5 = 3 };
+
+template <int MODE> struct GT;
+template <> struct GT<GM_F32> {
+  using TA = float;       // LDS element of both operands
   using acc = f32x4;
-  __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-  __device__ static inline acc step(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
+  static constexpr int KC = 32, NB = 1, SA = KC + 4;
+  // output layout of 16x16 products: lane l, register v -> D[row(l,v)][l%16]
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
-template <> struct Mfma<double> {
+template <> struct GT<GM_F64> {
+  using TA = double;
   using acc = f64x4;
-  __device__ static inline int row(int lane, int v) { return 4 * v + (lane >> 4); }
-  __device__ static inline acc step(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
+  static constexpr int KC = 16, NB = 1, SA = KC + 2;
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct GT<GM_BF3> {
+  using TA = __bf16;
+  using acc = f32x4;
+  static constexpr int KC = 32, NB = 2, SA = KC + 8;
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <> struct GT<GM_BF5> {
+  using TA = __bf16;
+  using acc = f32x4;
+  static constexpr int KC = 32, NB = 3, SA = KC + 8;
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-template <class TA, class TI, class TO>
 struct GemmArgs {
-  const TA* ops;
-  int64_t op_stride;
-  int ld, n_rhs, accumulate;
-  const TI* in;
-  TO* out;
+  const void* ops;      // FP32/FP64: [nop][ld][ld]; BF: high parts [nop][ld][ld]
+  const void* ops_lo;   // BF: low parts
+  int64_t op_stride;    // elements between operators (0: one operator)
+  int ld, n_rhs, accumulate, TB;
+  const void* in;       // columns [ncol][ld] of TI
+  void* out;            // columns [ncol][ld] of TO
   const int32_t* tile_cols;
   const int32_t* step_beg;
   const int32_t* step_op;
   const int32_t* step_src;
-  int TB;
 };
 
-constexpr int kTC = 64, kKC = 16, kRBMAX = 10, kROWS = kRBMAX * 16;
+constexpr int kRB = 10, kROWS = kRB * 16;
 
-template <class TA, class TI, class TO>
-__global__ __launch_bounds__(256) void gemm_plan_kernel(GemmArgs<TA, TI, TO> a) {
-  using M = Mfma<TA>;
-  __shared__ TA As[kROWS][kKC + 1];
-  __shared__ TA Bs[kTC][kKC + 1];
-  __shared__ int s_cols[kTC];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+template <int MODE, class TI, class TO, int CB>
+struct GemmCfg {
+  using G = GT<MODE>;
+  using TA = typename G::TA;
+  static constexpr int KC = G::KC, SA = G::SA, NB = G::NB, TC = 64 * CB;
+  static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5) ? 2 : 1;  // operator tables
+  // per buffer: NA operator tiles [ROWS][SA] and NB column tiles [TC][SA] of TA
+  static constexpr int A_ELEMS = NA * kROWS * SA, B_ELEMS = NB * TC * SA;
+  static constexpr int BUF_BYTES = (A_ELEMS + B_ELEMS) * int(sizeof(TA));
+  // 16-byte global units per chunk
+  static constexpr int A_UNITS_ROW = KC * int(sizeof(TA)) / 16;         // per table row
+  static constexpr int A_UNITS = NA * kROWS * A_UNITS_ROW;
+  static constexpr int A_PER_T = (A_UNITS + 255) / 256;
+  static constexpr int B_UNITS_COL = KC * int(sizeof(TI)) / 16;
+  static constexpr int B_UNITS = TC * B_UNITS_COL;
+  static constexpr int B_PER_T = (B_UNITS + 255) / 256;
+};
+
+template <class T>
+__device__ inline void split_store(__bf16* dst_h, __bf16* dst_m, __bf16* dst_l, int nb, const T* v, int cnt) {
+  for (int i = 0; i < cnt; ++i) {
+    float x = float(v[i]);
+    __bf16 h = __bf16(x);
+    float r = x - float(h);
+    __bf16 m = __bf16(r);
+    if (nb == 2) {
+      dst_h[i] = h;
+      dst_l[i] = m;
+    } else {
+      float r2 = r - float(m);
+      dst_h[i] = h;
+      dst_m[i] = m;
+      dst_l[i] = __bf16(r2);
+    }
+  }
+}
+
+template <int MODE, class TI, class TO, int CB>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
+  using Cfg = GemmCfg<MODE, TI, TO, CB>;
+  using G = GT<MODE>;
+  using TA = typename Cfg::TA;
+  using ACC = typename G::acc;
+  constexpr int KC = Cfg::KC, SA = Cfg::SA, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
+  constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5);
+  __shared__ __align__(16) unsigned char smem[2 * Cfg::BUF_BYTES];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int tile = blockIdx.x;
   const int row0 = blockIdx.y * kROWS;
-  const int nrb = min(kRBMAX, (a.ld - row0) / 16);
-  typename M::acc acc[kRBMAX];
-#pragma unroll
-  for (int i = 0; i < kRBMAX; ++i)
-    for (int v = 0; v < 4; ++v) acc[i][v] = TA(0);
-
+  const int nrb = min(kRB, (a.ld - row0) / 16);
+  const int ld = a.ld;
   const int ncols = a.TB * a.n_rhs;
   const int sb = a.step_beg[tile], se = a.step_beg[tile + 1];
-  for (int st = sb; st < se; ++st) {
+  const int kcs = ld / KC;  // chunks per step
+  const int nchunks = (se - sb) * kcs;
+
+  ACC acc[kRB][CB];
+#pragma unroll
+  for (int i = 0; i < kRB; ++i)
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][c][v] = 0;
+
+  uint4 ra[Cfg::A_PER_T], rb[Cfg::B_PER_T];
+  int64_t bcol[Cfg::B_PER_T];
+  int cur_step = -1;
+
+  auto load_regs = [&](int ch) {
+    const int st = sb + ch / kcs;
+    const int k0 = (ch % kcs) * KC;
     const int64_t opoff = int64_t(a.step_op[st]) * a.op_stride;
-    __syncthreads();
-    if (tid < kTC) {
-      int c = -1;
-      if (tid < ncols) {
-        int b = tid / a.n_rhs, r = tid % a.n_rhs;
-        int src = a.step_src[int64_t(st) * a.TB + b];
-        if (src >= 0) c = src * a.n_rhs + r;
+#pragma unroll
+    for (int j = 0; j < Cfg::A_PER_T; ++j) {
+      const int u = tid + j * 256;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (u < Cfg::A_UNITS) {
+        const int t = u / (kROWS * Cfg::A_UNITS_ROW);
+        const int uu = u % (kROWS * Cfg::A_UNITS_ROW);
+        const int row = row0 + uu / Cfg::A_UNITS_ROW, part = uu % Cfg::A_UNITS_ROW;
+        if (row < ld) {
+          const TA* base = static_cast<const TA*>(t == 0 ? a.ops : a.ops_lo);
+          v = *reinterpret_cast<const uint4*>(base + opoff + int64_t(row) * ld + k0 + part * (16 / int(sizeof(TA))));
+        }
       }
-      s_cols[tid] = c;
+      ra[j] = v;
     }
+    if (st != cur_step) {
+      // source columns of this thread's B units for the new step
+      cur_step = st;
+#pragma unroll
+      for (int j = 0; j < Cfg::B_PER_T; ++j) {
+        const int u = tid + j * 256;
+        const int s = u / Cfg::B_UNITS_COL;
+        int64_t col = -1;
+        if (u < Cfg::B_UNITS && s < ncols) {
+          const int src = a.step_src[int64_t(st) * a.TB + s / a.n_rhs];
+          if (src >= 0) col = int64_t(src) * a.n_rhs + s % a.n_rhs;
+        }
+        bcol[j] = col;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < Cfg::B_PER_T; ++j) {
+      const int part = (tid + j * 256) % Cfg::B_UNITS_COL;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (bcol[j] >= 0)
+        v = *reinterpret_cast<const uint4*>(static_cast<const TI*>(a.in) + bcol[j] * ld + k0 +
+                                            part * (16 / int(sizeof(TI))));
+      rb[j] = v;
+    }
+  };
+
+  auto store_lds = [&](int buf) {
+    TA* As = reinterpret_cast<TA*>(smem + buf * Cfg::BUF_BYTES);
+    TA* Bs = As + Cfg::A_ELEMS;
+#pragma unroll
+    for (int j = 0; j < Cfg::A_PER_T; ++j) {
+      const int u = tid + j * 256;
+      if (u < Cfg::A_UNITS) {
+        const int t = u / (kROWS * Cfg::A_UNITS_ROW);
+        const int uu = u % (kROWS * Cfg::A_UNITS_ROW);
+        const int i = uu / Cfg::A_UNITS_ROW, part = uu % Cfg::A_UNITS_ROW;
+        *reinterpret_cast<uint4*>(As + t * kROWS * SA + i * SA + part * (16 / int(sizeof(TA)))) = ra[j];
+      }
+    }
+    constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
+#pragma unroll
+    for (int j = 0; j < Cfg::B_PER_T; ++j) {
+      const int u = tid + j * 256;
+      if (u < Cfg::B_UNITS) {
+        const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
+        const TI* vals = reinterpret_cast<const TI*>(&rb[j]);
+        if constexpr (BF) {
+          __bf16* h = Bs + s * SA + part * EPU;
+          __bf16* m = h + TC * SA;
+          __bf16* l = h + (NB - 1) * TC * SA;
+          split_store(h, m, l, NB, vals, EPU);
+        } else {
+          TA* d = Bs + s * SA + part * EPU;
+#pragma unroll
+          for (int e = 0; e < EPU; ++e) d[e] = TA(vals[e]);
+        }
+      }
+    }
+  };
+
+  auto compute = [&](int buf) {
+    const TA* As = reinterpret_cast<const TA*>(smem + buf * Cfg::BUF_BYTES);
+    const TA* Bs = As + Cfg::A_ELEMS;
+    constexpr int KL = KC / 4;  // k values per lane per chunk
+    if constexpr (!BF) {
+      // all fragments of the chunk first, then k-outer / row-block-inner so
+      // that consecutive MFMAs accumulate into different registers
+      TA bv[CB][KL], av[kRB][KL];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const TA* p = Bs + (wave * 16 * CB + c * 16 + r16) * SA + g * KL;
+#pragma unroll
+        for (int e = 0; e < KL; ++e) bv[c][e] = p[e];
+      }
+      // rows past ld are staged as zeros, so every row block is computed
+      // unconditionally; only the epilogue skips them
+#pragma unroll
+      for (int i = 0; i < kRB; ++i) {
+        const TA* p = As + (i * 16 + r16) * SA + g * KL;
+#pragma unroll
+        for (int e = 0; e < KL; ++e) av[i][e] = p[e];
+      }
+#pragma unroll
+      for (int e = 0; e < KL; ++e)
+#pragma unroll
+        for (int i = 0; i < kRB; ++i)
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+              if constexpr (MODE == GM_F32)
+                acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][e], bv[c][e], acc[i][c], 0, 0, 0);
+              else
+                acc[i][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv[c][e], acc[i][c], 0, 0, 0);
+            }
+    } else {
+      bf16x8 bh[CB], bm[CB], bl[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int col = wave * 16 * CB + c * 16 + r16;
+        bh[c] = *reinterpret_cast<const bf16x8*>(Bs + col * SA + g * 8);
+        bl[c] = *reinterpret_cast<const bf16x8*>(Bs + (NB - 1) * TC * SA + col * SA + g * 8);
+        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const bf16x8*>(Bs + TC * SA + col * SA + g * 8);
+      }
+#pragma unroll
+      for (int i = 0; i < kRB; ++i) {
+        {
+          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(As + (i * 16 + r16) * SA + g * 8);
+          const bf16x8 al = *reinterpret_cast<const bf16x8*>(As + kROWS * SA + (i * 16 + r16) * SA + g * 8);
+#pragma unroll
+          for (int c = 0; c < CB; ++c) {
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[i][c], 0, 0, 0);
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[i][c], 0, 0, 0);
+            if constexpr (NB == 3) {
+              acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[c], acc[i][c], 0, 0, 0);
+              acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bm[c], acc[i][c], 0, 0, 0);
+            }
+            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[i][c], 0, 0, 0);
+          }
+        }
+      }
+    }
+  };
+
+  if (nchunks > 0) {
+    load_regs(0);
+    store_lds(0);
     __syncthreads();
-    for (int k0 = 0; k0 < a.ld; k0 += kKC) {
-      for (int e = tid; e < kROWS * kKC; e += 256) {
-        int i = e / kKC, kk = e % kKC, row = row0 + i;
-        As[i][kk] = row < a.ld ? a.ops[opoff + int64_t(row) * a.ld + k0 + kk] : TA(0);
-      }
-      for (int e = tid; e < kTC * kKC; e += 256) {
-        int s = e / kKC, kk = e % kKC, c = s_cols[s];
-        Bs[s][kk] = c >= 0 ? TA(a.in[int64_t(c) * a.ld + k0 + kk]) : TA(0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < kKC; kk += 4) {
-        const TA bv = Bs[wave * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-        for (int i = 0; i < kRBMAX; ++i)
-          if (i < nrb) acc[i] = M::step(As[i * 16 + (lane & 15)][kk + (lane >> 4)], bv, acc[i]);
-      }
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nchunks) load_regs(ch + 1);
+      compute(buf);
+      if (ch + 1 < nchunks) store_lds(buf ^ 1);
       __syncthreads();
     }
   }
-  const int s = wave * 16 + (lane & 15);
-  if (s < ncols) {
-    const int b = s / a.n_rhs, r = s % a.n_rhs;
-    const int box = a.tile_cols[int64_t(tile) * a.TB + b];
-    if (box >= 0) {
-      TO* o = a.out + (int64_t(box) * a.n_rhs + r) * a.ld;
+
 #pragma unroll
-      for (int i = 0; i < kRBMAX; ++i) {
-        if (i < nrb) {
+  for (int c = 0; c < CB; ++c) {
+    const int s = wave * 16 * CB + c * 16 + r16;
+    if (s < ncols) {
+      const int b = s / a.n_rhs, r = s % a.n_rhs;
+      const int box = a.tile_cols[int64_t(tile) * a.TB + b];
+      if (box >= 0) {
+        TO* o = static_cast<TO*>(a.out) + (int64_t(box) * a.n_rhs + r) * ld;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int row = row0 + i * 16 + M::row(lane, v);
-            TA val = acc[i][v];
-            if (a.accumulate) val += TA(o[row]);
-            o[row] = TO(val);
+        for (int i = 0; i < kRB; ++i) {
+          if (i < nrb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int row = row0 + i * 16 + G::row(lane, v);
+              using TAcc = decltype(acc[0][0][0] + 0);
+              TAcc val = acc[i][c][v];
+              if (a.accumulate) val += TAcc(o[row]);
+              o[row] = TO(val);
+            }
           }
         }
       }
@@ -775,16 +1000,22 @@ __global__ __launch_bounds__(256) void gemm_plan_kernel(GemmArgs<TA, TI, TO> a) 
 // pipeline
 // ------------------------------------------------------------------------
 
-template <class TA, class TI, class TO>
-static void run_gemm(const DevPlan& P, const TA* ops, int64_t op_stride, int ld, int n_rhs,
-                     const TI* in, TO* out, bool accumulate, hipStream_t s, PhaseScope& ps) {
+template <int MODE, class TI, class TO>
+static void run_gemm(const DevPlan& P, const void* ops, const void* ops_lo, int64_t op_stride,
+                     int ld, int n_rhs, const TI* in, TO* out, bool accumulate, hipStream_t s,
+                     PhaseScope& ps) {
   if (P.ntile == 0) return;
-  if (P.TB * n_rhs > kTC) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
-  GemmArgs<TA, TI, TO> g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, in, out,
-                         P.tile_cols, P.step_beg, P.step_op, P.step_src, P.TB};
+  const int ncols = P.TB * n_rhs;
+  if (ncols > 128) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
+  if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
+  GemmArgs g{ops, ops_lo, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
+             P.tile_cols, P.step_beg, P.step_op, P.step_src};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
-  hipLaunchKernelGGL((gemm_plan_kernel<TA, TI, TO>), grid, dim3(256), 0, s, g);
-  LAUNCHCHECK("gemm_plan_kernel");
+  if (ncols > 64)
+    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1>), grid, dim3(256), 0, s, g);
+  LAUNCHCHECK("gemm_kernel");
   ps.launches++;
 }
 
@@ -805,7 +1036,8 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t
 
 template <class T, class TIO>
 static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* charges,
-                     void* const* potentials, int n_rhs, hipStream_t s) {
+                     void* const* potentials, int n_rhs, kifmm_precision prec, hipStream_t s) {
+  constexpr int GF = sizeof(T) == 8 ? GM_F64 : GM_F32;
   const int ld = F.ld;
   const int64_t nn = int64_t(ld) * ld;
   T* qs = static_cast<T*>(W.qs);
@@ -867,11 +1099,11 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   for (int l = F.depth; l >= 2; --l) {
     {
       PhaseScope ps(PH_M2M, s);
-      run_gemm<T, T, T>(F.m2m[l], m2m, nn, ld, n_rhs, up_eq, up_chk, false, s, ps);
+      run_gemm<GF, T, T>(F.m2m[l], m2m, nullptr, nn, ld, n_rhs, up_eq, up_chk, false, s, ps);
     }
     {
       PhaseScope ps(PH_UC2E, s);
-      run_gemm<double, T, T>(F.uc2e[l], O.uc2e, 0, ld, n_rhs, up_chk, up_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, nullptr, 0, ld, n_rhs, up_chk, up_eq, false, s, ps);
     }
   }
   {
@@ -889,16 +1121,25 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   }
   {
     PhaseScope ps(PH_M2L, s);
-    run_gemm<T, T, T>(F.m2l, m2l, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+    if constexpr (sizeof(T) == 8) {
+      run_gemm<GM_F64, T, T>(F.m2l, m2l, nullptr, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+    } else {
+      if (prec == KIFMM_M2L_BF16X3)
+        run_gemm<GM_BF3, T, T>(F.m2l, O.m2l_bh, O.m2l_bl, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+      else if (prec == KIFMM_M2L_BF16X5)
+        run_gemm<GM_BF5, T, T>(F.m2l, O.m2l_bh, O.m2l_bl, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+      else
+        run_gemm<GM_F32, T, T>(F.m2l, m2l, nullptr, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+    }
   }
   for (int l = 2; l <= F.depth; ++l) {
     if (l >= 3) {
       PhaseScope ps(PH_L2L, s);
-      run_gemm<T, T, T>(F.l2l[l], l2l, nn, ld, n_rhs, dn_eq, dn_chk, true, s, ps);
+      run_gemm<GF, T, T>(F.l2l[l], l2l, nullptr, nn, ld, n_rhs, dn_eq, dn_chk, true, s, ps);
     }
     {
       PhaseScope ps(PH_DC2E, s);
-      run_gemm<double, T, T>(F.dc2e[l], O.dc2e, 0, ld, n_rhs, dn_chk, dn_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e, nullptr, 0, ld, n_rhs, dn_chk, dn_eq, false, s, ps);
     }
   }
   {
@@ -936,20 +1177,18 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
     st.forest = upload_forest(*st.host, hops.n);
     st.device = dev;
   }
-  if (prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5)
-    raise(KIFMM_EUNSUPPORTED, "evaluate: split-BF16 M2L is not available in this build");
   const bool fp64 = prec == KIFMM_FP64;
-  DevOps* O = ops_for_device(oc, hops, dev, fp64);
+  DevOps* O = ops_for_device(oc, hops, dev, fp64, prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5);
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
   DevWork* W = work_for(F, fp64, n_rhs);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (fp64) {
-    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, s);
-    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, s);
+    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, s);
+    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, s);
   } else {
-    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, s);
-    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, s);
+    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, s);
+    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, s);
   }
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <set>
 
 #include "common.hpp"
 
@@ -51,7 +52,7 @@ Plan new_plan(int TB) {
 
 }  // namespace
 
-HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB) {
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm) {
   auto* Fp = new HostForest();
   HostForest& F = *Fp;
   F.nprob = n;
@@ -160,7 +161,7 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
   F.uc2e.assign(D + 1, new_plan(TB));
   F.l2l.assign(D + 1, new_plan(TB));
   F.dc2e.assign(D + 1, new_plan(TB));
-  F.m2l = new_plan(TB);
+  F.m2l = new_plan(TBm);
   for (int l = 2; l <= D; ++l) {
     // M2M: non-leaf parents with sources; step o takes the child of octant o
     std::vector<int32_t> parents, withsrc, withtgt;
@@ -230,9 +231,38 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
         }
       }
     }
-    auto tiles = group_tiles(tg, TB, [&](int32_t g) {
+    auto tiles = group_tiles(tg, TBm, [&](int32_t g) {
       return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g];
     });
+    // Launch order: blocks are dealt to the 8 XCDs round-robin, so tile t is
+    // given octant class t % 8 while every class has tiles left: the blocks
+    // resident on one XCD then walk the same operator sequence and share it
+    // through that XCD's L2.  Inside a class, tiles with more steps go first.
+    {
+      std::array<std::vector<std::vector<int32_t>>, 8> q;
+      for (auto& t : tiles) q[F.box_octant[t[0]]].push_back(t);
+      auto cost = [&](const std::vector<int32_t>& t) {
+        std::set<int32_t> ops;
+        for (int32_t g : t)
+          for (auto& e : vl[g]) ops.insert(e.first);
+        return ops.size();
+      };
+      for (auto& v : q)
+        std::stable_sort(v.begin(), v.end(), [&](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
+          return cost(x) > cost(y);
+        });
+      std::vector<std::vector<int32_t>> order;
+      std::array<size_t, 8> pos{};
+      for (bool any = true; any;) {
+        any = false;
+        for (int o = 0; o < 8; ++o)
+          if (pos[o] < q[o].size()) {
+            order.push_back(q[o][pos[o]++]);
+            any = true;
+          }
+      }
+      tiles.swap(order);
+    }
     for (auto& tile : tiles) {
       std::map<int32_t, std::vector<int32_t>> steps;
       for (size_t j = 0; j < tile.size(); ++j)

@@ -56,7 +56,8 @@ struct HostForest {
   int64_t p2p_interactions = 0;  // sum over U pairs of n_tgt(B) * n_src(A)
 };
 
-// Builds the forest of `n` trees for operator set `ops` and plan width TB.
-HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB);
+// Builds the forest of `n` trees for operator set `ops`: plan width TB boxes
+// per tile for M2M, L2L and the solves, TBm for M2L.
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm);
 
 }  // namespace kifmm

@@ -45,7 +45,7 @@ EXPORTED = [
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_precompute_operators",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
-    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
+    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
 
 
@@ -78,6 +78,7 @@ def lib():
     L.kifmm_phase_name.restype = C.c_char_p
     L.kifmm_get_phase_times.argtypes = [D, C.POINTER(I64)]
     L.kifmm_debug_buffer.argtypes = [P, I32, I32, I32, D, I64]
+    L.kifmm_set_tuning.argtypes = [C.c_char_p, I32]
     L.kifmm_tree_destroy.argtypes = [P]
     L.kifmm_tree_destroy.restype = None
     L.kifmm_ops_destroy.argtypes = [P]
@@ -263,6 +264,11 @@ def evaluate_simple(src, q, tgt, p: int) -> np.ndarray:
     _check(lib().kifmm_evaluate_simple(_dptr(src), _dptr(q), len(src), _dptr(tgt), len(tgt), p,
                                        _dptr(pot)))
     return pot
+
+
+def set_tuning(key: str, value: int):
+    """Process-wide kernel tuning knob (see kifmm_set_tuning)."""
+    _check(lib().kifmm_set_tuning(key.encode(), int(value)))
 
 
 def set_profiling(on: bool):

@@ -5,7 +5,8 @@ Tolerances (relative L2 over all compared targets):
     pseudo-inverse (Jacobi SVD vs LAPACK); with rcond = 1e-9 the operators
     agree only to ~1e-8 and the fields to ~1e-9 (measured spread between two
     correct SVD drivers), so 1e-8 is the floor a correct FP64 path can meet.
-  FP32 GPU vs FP64 oracle: 1e-5 (the accuracy target of the FP32 path).
+  FP32 and split-BF16 M2L vs FP64 oracle: 1e-5 (the accuracy target of the
+    mixed-precision paths).
 """
 import numpy as np
 import pytest
@@ -20,6 +21,7 @@ from paper_2303_08394_amd import kifmm as K  # noqa: E402
 
 CUBE = dict(center=(0.5, 0.5, 0.5), halfwidth=0.5)
 TOL64, TOL32 = 1e-8, 1e-5
+TOL = {"fp64": TOL64, "fp32": TOL32, "bf16x3": TOL32, "bf16x5": TOL32}
 DEV = "cuda:0"
 
 
@@ -70,7 +72,7 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16x5"])
 def test_parity_vs_oracle(name, precision):
     x, q, tgt, p, kw = _case(name)
     want = oracle(name, x, q, tgt, p, **kw)
@@ -78,7 +80,7 @@ def test_parity_vs_oracle(name, precision):
     got = gpu_eval(tree, p, q, precision)
     e = rel(got, want)
     print(f"{name} {precision} rel L2 vs oracle = {e:.3e}")
-    assert e < (TOL64 if precision == "fp64" else TOL32)
+    assert e < TOL[precision]
 
 
 def test_fp32_io_and_separate_targets():
