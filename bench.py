@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12   # dense FP32 matrix FLOP/s
 PEAK_FP64_MFMA = 78.6e12
-PEAK_BF16_MFMA = 2.5e15     # dense BF16 matrix FLOP/s
+PEAK_BF16_MFMA = 2.5e15     # dense BF16 / FP16 matrix FLOP/s
 PEAK_HBM = 8.0e12
 # The particle kernels are bound by plain FP32 VALU issue: 256 CUs x 4 SIMDs x
 # 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s.  One pair interaction issues
@@ -37,12 +37,68 @@ SLOTS_PER_PAIR = 13.0
 PEAK_PAIRS = VALU_LANE_OPS / SLOTS_PER_PAIR
 
 
-def _workload(args):
+def _work_counts(tree, pn):
+    """(V-list pairs, near-field pair interactions, leaf far-field pairs)."""
+    from paper_2303_08394_amd import kifmm as K
+    bx = tree.boxes()
+    nt = bx["tgt_range"][:, 1] - bx["tgt_range"][:, 0]
+    ns = bx["src_range"][:, 1] - bx["src_range"][:, 0]
+    uoff, uitems = tree.list(K.LIST_U)
+    woff, _ = tree.list(K.LIST_W)
+    per_box_src = np.zeros(len(nt), np.int64)
+    nz = np.nonzero(np.diff(uoff))[0]
+    if len(uitems):
+        per_box_src[nz] = np.add.reduceat(ns[uitems], uoff[nz])
+    leaves = bx["is_leaf"] == 1
+    near = int((nt * per_box_src)[leaves].sum())
+    far = int(nt[leaves & (bx["level"] >= 2)].sum()) * pn + int((nt * np.diff(woff))[leaves].sum()) * pn
+    return int(tree.info().n_v), near, far
+
+
+def _kernel_source_sha() -> str:
+    import hashlib
+    p = os.path.join(ROOT, "paper_2303_08394_amd", "csrc", "evaluate.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def _measured_traffic(precision: str):
+    """HBM bytes per M2L launch from the committed rocprofv3 PMC summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the summary is missing or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "m2l_traffic_uniform1m_p6.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("evaluate_hip_sha256_16") != _kernel_source_sha():
+        return None
+    key = f"traffic_bytes_{precision}"
+    return float(kv[key]) if key in kv else None
+
+
+# Headline mixed mode: FP32 bulk, FP64 solves and per-target sums, M2L as
+# three split-FP16 products with FP32 accumulation (meets the 1e-5 target at
+# p = 6 with a 4x margin; BF16x3 does not, see DESIGN.md).
+DEFAULT_PRECISION = {"uniform_1m": "f16x3", "plain_20k": "fp64", "sphere_4m": "bf16x3",
+                     "batch_64": "fp32", "multi_rhs_1m": "f16x3"}
+
+
+def _problems(args):
+    """The workload's problems (one, or the 64 of the batch)."""
     from paper_2303_08394_amd import inputs as I
     if args.config == "uniform_1m":
-        return I.uniform_1m()
-    if args.config == "uniform_20k":
-        return I.plain_fp64_20k()
+        return [I.uniform_1m()]
+    if args.config == "plain_20k":
+        return [I.plain_fp64_20k()]
+    if args.config == "sphere_4m":
+        return [I.sphere_4m()]
+    if args.config == "batch_64":
+        return [I.batch_problem(k) for k in range(64)]
+    if args.config == "multi_rhs_1m":
+        return [I.multi_rhs_1m()]
     raise SystemExit(f"unknown config {args.config}")
 
 
@@ -75,12 +131,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="uniform_1m")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16x5", "fp64"])
+    ap.add_argument("--config", default="uniform_1m",
+                    choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16x3", "bf16x5", "f16x3", "fp64", "fp64+m2l_fp32", "fp64+m2l_f16x3"])
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-sample", type=int, default=200)
     ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128)")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build evaluates on one GPU; --gpus {args.gpus} is not supported "
@@ -95,49 +154,90 @@ def main():
 
     if args.m2l_tile:
         K.set_tuning("m2l_tile_cols", args.m2l_tile)
-    prob = _workload(args)
+    if args.copy_probe:
+        # plain device copy of known size, read from HBM: the source is pushed
+        # out of L2 and the 256 MB Infinity Cache by a 1 GiB fill first
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0")
+        flush.fill_(2.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst, flush
+    probs = _problems(args)
+    batch = len(probs) > 1
+    prob = probs[0]
     t0 = time.perf_counter()
-    tree = K.Tree(prob.points, uniform_depth=prob.uniform_depth, ncrit=prob.ncrit,
-                  max_depth=prob.max_depth, center=prob.center, halfwidth=prob.halfwidth)
+    trees = [K.Tree(p.points, uniform_depth=p.uniform_depth, ncrit=p.ncrit, max_depth=p.max_depth,
+                    center=p.center, halfwidth=p.halfwidth) for p in probs]
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
     ops = K.Operators(prob.p)
     t_ops = time.perf_counter() - t0
+    tree = trees[0]
     info = tree.info()
     dev = torch.device("cuda:0")
-    q = torch.as_tensor(prob.charges, dtype=torch.float64, device=dev)
+    qs = [torch.as_tensor(p.charges, dtype=torch.float64, device=dev) for p in probs]
+    n_total = sum(p.n for p in probs)
+    n_rhs = prob.charges.shape[0]
     n = prob.n
-    stream = torch.cuda.current_stream()
+
+    def evaluate_all(precision, outs):
+        if batch:
+            K.evaluate_batch(trees, ops, [q[0] for q in qs], precision=precision, outs=outs)
+        else:
+            K.evaluate(tree, ops, qs[0], precision=precision, out=outs[0])
 
     def run(precision, steps, warmup):
-        out = torch.empty((q.shape[0], n), dtype=torch.float64, device=dev)
+        if batch:
+            outs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs]
+        else:
+            outs = [torch.empty((n_rhs, n), dtype=torch.float64, device=dev)]
         for _ in range(warmup):
-            K.evaluate(tree, ops, q, precision=precision, out=out)
+            evaluate_all(precision, outs)
         torch.cuda.synchronize()
         K.phase_times()
         K.set_profiling(True)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for _ in range(steps):
-            K.evaluate(tree, ops, q, precision=precision, out=out)
+            evaluate_all(precision, outs)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         K.set_profiling(False)
         ph = K.phase_times()
-        return out, (tb - ta) / steps, ph
+        return [o.reshape(-1, o.shape[-1]).cpu().numpy() for o in outs], (tb - ta) / steps, ph
 
-    out, t_step, phases = run(args.precision, args.steps, args.warmup)
-    res = out[0].double().cpu().numpy()
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    precision = args.precision or DEFAULT_PRECISION[args.config]
+    res, t_step, phases = run(precision, args.steps, args.warmup)
     result = {}
-    if not args.no_fp64_leg and args.precision != "fp64":
-        ref, t64, ph64 = run("fp64", max(3, args.steps // 4), 1)
-        ref = ref[0].cpu().numpy()
+    if not args.no_fp64_leg and precision != "fp64" and args.config != "multi_rhs_1m":
+        ref, t64, ph64 = run("fp64", max(2, args.steps // 4), 1)
         result["fp64_ms_per_step"] = t64 * 1e3
         result["speedup_vs_fp64"] = t64 / t_step
-        result["rel_l2_vs_fp64_gpu"] = float(np.linalg.norm(res - ref) / np.linalg.norm(ref))
+        result["rel_l2_vs_fp64_gpu"] = rel(np.concatenate([r.ravel() for r in res]),
+                                           np.concatenate([r.ravel() for r in ref]))
+    elif not args.no_fp64_leg and precision != "fp64":
+        # multi-RHS: the FP64 reference runs once (it takes seconds at p = 10)
+        ref, t64, ph64 = run("fp64", 1, 0)
+        result["fp64_ms_per_step"] = t64 * 1e3
+        result["speedup_vs_fp64"] = t64 / t_step
+        result["rel_l2_vs_fp64_gpu"] = rel(res[0], ref[0])
+    # direct sum on a seeded sample of targets (first problem, first charge vector)
     idx = I.sample_indices(n, args.direct_sample)
     exact = direct.direct(prob.points, prob.charges[0], prob.points[idx])
-    result["rel_l2_vs_direct_sample"] = float(np.linalg.norm(res[idx] - exact) / np.linalg.norm(exact))
+    result["rel_l2_vs_direct_sample"] = rel(res[0][0][idx], exact)
+    if args.config == "plain_20k":
+        from oracle import kifmm as OK
+        from oracle.octree import Octree
+        want = OK.KIFMM(Octree(prob.points, prob.points, uniform_depth=prob.uniform_depth,
+                               center=prob.center, halfwidth=prob.halfwidth), prob.p).evaluate(prob.charges)
+        result["rel_l2_vs_oracle"] = rel(res[0], want)
+        result["oracle_rel_l2_vs_direct"] = rel(want[0], direct.direct(prob.points, prob.charges[0], prob.points))
 
     # roofline of the dominant kernel
     nrun = args.steps
@@ -145,41 +245,35 @@ def main():
     launches = {k: v[1] / nrun for k, v in phases.items()}
     dom = max(ms, key=ms.get)
     pn = ops.n
-    v_pairs = info.n_v
-    flops_m2l = 2.0 * pn * pn * v_pairs
-    # P2P pair interactions of the fused leaf kernel: near field + L2P (+ M2P)
-    bx = tree.boxes()
-    uoff, uitems = tree.list(K.LIST_U)
-    nt = bx["tgt_range"][:, 1] - bx["tgt_range"][:, 0]
-    ns = bx["src_range"][:, 1] - bx["src_range"][:, 0]
-    leaves = np.nonzero(bx["is_leaf"] == 1)[0]
-    near_pairs = 0
-    for b in leaves:
-        near_pairs += int(nt[b]) * int(ns[uitems[uoff[b]:uoff[b + 1]]].sum())
-    woff, witems = tree.list(K.LIST_W)
-    far_pairs = int(nt[leaves][bx["level"][leaves] >= 2].sum()) * pn + \
-        int(sum(nt[b] * (woff[b + 1] - woff[b]) for b in leaves)) * pn
-    leaf_pairs = near_pairs + far_pairs
+    v_pairs = near_pairs = far_pairs = 0
+    for t in trees:
+        w = _work_counts(t, pn)
+        v_pairs += w[0]
+        near_pairs += w[1]
+        far_pairs += w[2]
+    flops_m2l = 2.0 * pn * pn * v_pairs * n_rhs
+    leaf_pairs = (near_pairs + far_pairs) * n_rhs
     if dom == "m2l":
         # algorithmic flops (one product per V-list pair), against the peak of
         # the instruction the path issues; split-BF16 issues 3 (5) products
+        m2l_kind = precision.split("m2l_")[-1]
         peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
-                "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA}[args.precision]
-        issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5}[args.precision]
+                "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
+        issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
         roof = {"kernel": "gemm_kernel (M2L)", "bound": "mfma",
-                "achieved": flops_m2l / (ms["m2l"] * 1e-3) / 1e12,
+                "achieved": flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s",
-                "issued_frac": issued * flops_m2l / (ms["m2l"] * 1e-3) / peak}
+                "issued_frac": issued * flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / peak}
     else:
-        roof = {"kernel": f"{dom}", "bound": "alu",
-                "achieved": leaf_pairs / (ms["leaf"] * 1e-3) / 1e12,
+        roof = {"kernel": "p2p_kernel (leaf)", "bound": "alu",
+                "achieved": leaf_pairs / (ms["leaf"] / launches["leaf"] * 1e-3) / 1e12,
                 "peak": PEAK_PAIRS / 1e12, "unit": "Tpairs/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
 
     line = {
         "metric": "FMM evaluate Mpoints/s at 1M pts p=6, rel L2 err<=1e-5; mixed vs plain FP64",
-        "value": n / t_step / 1e6,
+        "value": n_total / t_step / 1e6,
         "unit": "Mpoints/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -188,21 +282,25 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16x3": "bf16x3", "bf16x5": "bf16x5", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3", "bf16x5": "f32+bf16x5", "f16x3": "f32+f16x3",
+                  "fp64": "f64", "fp64+m2l_fp32": "f64+f32", "fp64+m2l_f16x3": "f64+f16x3"}[precision],
         "data": "synthetic",
-        "config": {"workload": prob.name, "n_points": n, "p": prob.p, "depth": info.depth,
-                   "leaves": info.n_leaves, "precision": args.precision},
+        "config": {"workload": prob.name if not batch else f"batch of {len(probs)} problems",
+                   "n_points": n_total, "n_rhs": n_rhs, "p": prob.p,
+                   "depth": max(t.info().depth for t in trees),
+                   "leaves": sum(t.info().n_leaves for t in trees), "precision": precision},
         "roofline": roof,
         "phases_ms": {k: round(v, 4) for k, v in ms.items()},
         "launches_per_step": {k: v for k, v in launches.items()},
-        "work": {"m2l_flop": flops_m2l, "v_pairs": v_pairs, "u_pairs": info.n_u,
-                 "near_pairs": near_pairs, "leaf_far_pairs": far_pairs},
+        "work": {"m2l_flop": flops_m2l, "v_pairs": v_pairs, "near_pairs": near_pairs,
+                 "leaf_far_pairs": far_pairs},
         "tree_build_s": t_tree,
         "precompute_s": t_ops,
         **result,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        if args.config == "uniform_1m":
+            line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
     return 0
 

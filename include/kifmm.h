@@ -43,14 +43,23 @@ typedef enum {
 
 /* Arithmetic of an evaluation.  In every mode the check-to-equivalent solves
  * (UC2E, DC2E) run in FP64 and the per-target sum of near and far field is
- * accumulated in FP64. */
+ * accumulated in FP64.  In the FP32-bulk modes the equivalent-surface terms
+ * (L2P, M2P) are computed in FP64 from order p >= 10 (tuning key
+ * "far_fp64_min_p"). */
 typedef enum {
   KIFMM_FP64 = 0,        /* every operator in FP64 */
   KIFMM_FP32 = 1,        /* particle operators, M2M, L2L, M2L in FP32 */
   KIFMM_M2L_BF16X3 = 2,  /* as FP32; M2L as A_h x_h + A_h x_l + A_l x_h, BF16
                             MFMA products accumulated in FP32 */
-  KIFMM_M2L_BF16X5 = 3   /* as FP32; M2L with the density split three ways:
+  KIFMM_M2L_BF16X5 = 3,  /* as FP32; M2L with the density split three ways:
                             A_h x_h + A_h x_m + A_l x_h + A_l x_m + A_h x_l */
+  KIFMM_M2L_F16X3 = 4,   /* as FP32; M2L as A_h x_h + A_h x_l + A_l x_h in FP16
+                            (11-bit significands) on MFMA, FP32 accumulation;
+                            operators and densities scaled by powers of two
+                            into FP16 range, so the scaling is exact */
+  KIFMM_FP64_M2L_FP32 = 5,  /* every operator in FP64 except M2L (FP32 MFMA) */
+  KIFMM_FP64_M2L_F16X3 = 6  /* every operator in FP64 except M2L (split FP16 as
+                               in KIFMM_M2L_F16X3) */
 } kifmm_precision;
 
 /* Octree parameters (section "Computational structure of FMM operators":
@@ -185,10 +194,21 @@ kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches);
 kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t fp64,
                                 int32_t n_rhs, double* out, int64_t n_out);
 
-/* Process-wide tuning knobs of the evaluation kernels, applied when an
- * evaluation next builds its device plans (a change rebuilds them).
- *   "m2l_tile_cols": output columns (box x right-hand side) per M2L block,
- *                    64 (default) or 128.
+/* Process-wide tuning knobs of the evaluation kernels (a change of a plan
+ * knob rebuilds the plans at the next evaluate).
+ *   "m2l_tile_cols":  output columns (box x right-hand side) per M2L block,
+ *                     64 (default) or 128.
+ *   "far_fp64_min_p": smallest order p at which FP32-bulk modes evaluate the
+ *                     equivalent-surface terms in FP64 (default 10; 2..17,
+ *                     17 = never).
+ *   "m2l_check_min_p": smallest order p at which the FP32 and split-FP16 M2L
+ *                     act on upward check potentials with the operators
+ *                     folded with UC2E (M2L_o * UC2E, formed in FP64) instead
+ *                     of on equivalent densities (default 10; 17 = never).
+ *   "m2l_fp64_sum_min_p": smallest order p at which an M2L that accumulates
+ *                     in FP32 (FP32, BF16 and FP16 products) moves its sums
+ *                     into FP64 after every operator step (default 10; 17 =
+ *                     never).
  * EINVAL for an unknown key or value. */
 kifmm_status kifmm_set_tuning(const char* key, int32_t value);
 

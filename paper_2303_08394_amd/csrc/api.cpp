@@ -84,7 +84,7 @@ static void check_eval_args(const kifmm_tree* tree, const kifmm_ops* ops, int32_
   if (!tree || !ops) raise(KIFMM_EINVAL, "evaluate: null tree or ops handle");
   if (n_rhs < 1) raise(KIFMM_EINVAL, "evaluate: n_rhs must be >= 1");
   if (n_rhs > 64) raise(KIFMM_EUNSUPPORTED, "evaluate: at most 64 right-hand sides per call");
-  if (prec < KIFMM_FP64 || prec > KIFMM_M2L_BF16X5) raise(KIFMM_EINVAL, "evaluate: unknown precision");
+  if (prec < KIFMM_FP64 || prec > KIFMM_FP64_M2L_F16X3) raise(KIFMM_EINVAL, "evaluate: unknown precision");
 }
 
 }  // namespace kifmm
@@ -299,6 +299,21 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
   if (std::strcmp(key, "m2l_tile_cols") == 0) {
     if (value != 64 && value != 128) return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64 or 128");
     g_m2l_tile_cols = value;
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "m2l_fp64_sum_min_p") == 0) {
+    if (value < 2 || value > 17) return fail(KIFMM_EINVAL, "set_tuning: m2l_fp64_sum_min_p must be in [2, 17]");
+    set_m2l_fp64_sum_min_p(value);
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "m2l_check_min_p") == 0) {
+    if (value < 2 || value > 17) return fail(KIFMM_EINVAL, "set_tuning: m2l_check_min_p must be in [2, 17]");
+    set_m2l_check_min_p(value);
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "far_fp64_min_p") == 0) {
+    if (value < 2 || value > 17) return fail(KIFMM_EINVAL, "set_tuning: far_fp64_min_p must be in [2, 17]");
+    set_far_fp64_min_p(value);
     return KIFMM_OK;
   }
   return fail(KIFMM_EINVAL, std::string("set_tuning: unknown key ") + key);

@@ -51,6 +51,14 @@ void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, i
 
 int current_device();
 
+// smallest order at which FP32-bulk modes evaluate L2P/M2P terms in FP64
+void set_far_fp64_min_p(int p);
+// smallest order at which FP32/FP16 M2L runs on check potentials with the
+// operators folded with UC2E
+void set_m2l_check_min_p(int p);
+// smallest order at which FP32-accumulating M2L sums its steps in FP64
+void set_m2l_fp64_sum_min_p(int p);
+
 // profiling
 void set_profiling(bool on);
 int n_phases();

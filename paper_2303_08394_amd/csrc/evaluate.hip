@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -39,17 +40,25 @@ namespace kifmm {
 
 static constexpr double kInv4Pi = 0.0795774715459476678844418816863;
 static constexpr double kRin = 1.05, kRout = 2.95;
+// FP16 split M2L: operators are stored times 2^kF16OpExp (their entries are
+// O(1e-2), so both parts stay normal FP16 numbers); densities are scaled by
+// 2^e with e chosen from their largest magnitude so that it maps below 2^14.
+constexpr int kF16OpExp = 10;
 
 // ------------------------------------------------------------------------
 // device state
 // ------------------------------------------------------------------------
 
 struct DevOps {
-  int n = 0, ld = 0;
+  int n = 0, ld = 0, p = 0;
   double *uc2e = nullptr, *dc2e = nullptr;               // [ld][ld]
   float *m2m32 = nullptr, *l2l32 = nullptr, *m2l32 = nullptr;  // [k][ld][ld]
   double *m2m64 = nullptr, *l2l64 = nullptr, *m2l64 = nullptr;
   uint16_t *m2l_bh = nullptr, *m2l_bl = nullptr;         // BF16 high/low parts of M2L
+  uint16_t *m2l_hh = nullptr, *m2l_hl = nullptr;         // FP16 parts of 2^10 M2L
+  // check-potential form (M2L folded with UC2E): FP32 and FP16 parts
+  float* m2lc32 = nullptr;
+  uint16_t *m2lc_hh = nullptr, *m2lc_hl = nullptr;
   double4* surf = nullptr;                               // [n] unit-cube surface
   std::vector<void*> allocs;
   ~DevOps() {
@@ -66,6 +75,7 @@ struct DevWork {
   void* dn_chk = nullptr;
   void* dn_eq = nullptr;
   double* pot = nullptr;    // [n_rhs][ntgt]
+  unsigned* absmax = nullptr;  // [4] scratch word for the FP16 density scale
   size_t col_bytes = 0;
   std::vector<void*> allocs;
   ~DevWork() {
@@ -81,7 +91,6 @@ struct DevForest {
   double* box_r = nullptr;
   int2 *box_src = nullptr, *box_tgt = nullptr;
   double4 *src64 = nullptr, *tgt64 = nullptr;
-  float4* tgt32 = nullptr;
   int32_t *src_perm = nullptr, *tgt_perm = nullptr;
   int64_t *src_off = nullptr, *tgt_off = nullptr;
   int32_t *p2m_boxes = nullptr, *leaf_boxes = nullptr, *u_off = nullptr, *u_items = nullptr;
@@ -164,7 +173,6 @@ static DevForest* upload_forest(const HostForest& F, int n) {
     D->box_tgt = dev_upload<int2>(A, F.box_tgt);
     D->src64 = dev_upload<double4>(A, F.src_f64);
     D->tgt64 = dev_upload<double4>(A, F.tgt_f64);
-    D->tgt32 = dev_upload<float4>(A, F.tgt_f32);
     D->src_perm = dev_upload<int32_t>(A, F.src_perm);
     D->tgt_perm = dev_upload<int32_t>(A, F.tgt_perm);
     D->src_off = dev_upload<int64_t>(A, F.src_off);
@@ -222,11 +230,53 @@ static double bf16_value(uint16_t b) {
   return f;
 }
 
-static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64, bool bf16) {
+static uint16_t f16_bits(double x) {
+  _Float16 h = _Float16(float(x));
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+static double f16_value(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return double(float(h));
+}
+
+// M2L runs on check potentials with the folded operators from this order on
+// (their cancellation is ~10x smaller than the densities' at p = 10, larger
+// at p <= 8).
+static int g_m2l_check_min_p = 10;
+void set_m2l_check_min_p(int p) { g_m2l_check_min_p = p; }
+// FP32-accumulating M2L moves its sums into FP64 after every operator step
+// from this order on (it costs occupancy; at p = 10 it cuts the error ~10x).
+static int g_m2l_fp64_sum_min_p = 10;
+void set_m2l_fp64_sum_min_p(int p) { g_m2l_fp64_sum_min_p = p; }
+
+static void upload_split16(DevOps* O, const std::vector<double>& pad, uint16_t** hi_out,
+                           uint16_t** lo_out) {
+  std::vector<uint16_t> hi(pad.size()), lo(pad.size());
+  const double sc = std::ldexp(1.0, kF16OpExp);
+  for (size_t i = 0; i < pad.size(); ++i) {
+    const double v = pad[i] * sc;
+    hi[i] = f16_bits(v);
+    lo[i] = f16_bits(v - f16_value(hi[i]));
+  }
+  *hi_out = dev_upload<uint16_t>(O->allocs, hi);
+  *lo_out = dev_upload<uint16_t>(O->allocs, lo);
+}
+
+// Which tables an evaluation needs: bulk type (FP32 or FP64 M2M/L2L), and the
+// M2L operand: FP64, FP32, BF16 split or FP16 split, in density or check form.
+struct OpsNeed {
+  bool bulk64 = false, m2l64 = false, m2l32 = false, bf16 = false, f16 = false, check_form = false;
+};
+
+static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const OpsNeed& need) {
   DevOps*& O = oc.per_device[dev];
   if (!O) {
     O = new DevOps();
     O->n = H.n;
+    O->p = H.p;
     O->ld = round32(H.n);
     O->uc2e = dev_upload<double>(O->allocs, pad_table<double>(H.uc2e, 1, H.n, O->ld));
     O->dc2e = dev_upload<double>(O->allocs, pad_table<double>(H.dc2e, 1, H.n, O->ld));
@@ -235,12 +285,34 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64
       for (int d = 0; d < 3; ++d) s4[4 * i + d] = H.surf[3 * i + d];
     O->surf = dev_upload<double4>(O->allocs, s4);
   }
-  if (fp64 && !O->m2l64) {
+  if (need.bulk64 && !O->m2m64) {
     O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8, H.n, O->ld));
     O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8, H.n, O->ld));
-    O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
   }
-  if (bf16 && !O->m2l_bh) {
+  if (!need.bulk64 && !O->m2m32) {
+    O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8, H.n, O->ld));
+    O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8, H.n, O->ld));
+  }
+  if (need.m2l64 && !O->m2l64)
+    O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
+  if (need.check_form) {
+    if ((need.f16 && !O->m2lc_hh) || (need.m2l32 && !O->m2lc32)) {
+      std::vector<double> pad = pad_table<double>(m2l_check_form(H), kNumM2L, H.n, O->ld);
+      if (need.f16 && !O->m2lc_hh) upload_split16(O, pad, &O->m2lc_hh, &O->m2lc_hl);
+      if (need.m2l32 && !O->m2lc32) {
+        std::vector<float> f(pad.begin(), pad.end());
+        O->m2lc32 = dev_upload<float>(O->allocs, f);
+      }
+    }
+  } else {
+    if (need.m2l32 && !O->m2l32)
+      O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L, H.n, O->ld));
+    if (need.f16 && !O->m2l_hh) {
+      std::vector<double> pad = pad_table<double>(H.m2l, kNumM2L, H.n, O->ld);
+      upload_split16(O, pad, &O->m2l_hh, &O->m2l_hl);
+    }
+  }
+  if (need.bf16 && !O->m2l_bh) {
     std::vector<double> pad = pad_table<double>(H.m2l, kNumM2L, H.n, O->ld);
     std::vector<uint16_t> hi(pad.size()), lo(pad.size());
     for (size_t i = 0; i < pad.size(); ++i) {
@@ -249,11 +321,6 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, bool fp64
     }
     O->m2l_bh = dev_upload<uint16_t>(O->allocs, hi);
     O->m2l_bl = dev_upload<uint16_t>(O->allocs, lo);
-  }
-  if (!fp64 && !O->m2l32) {
-    O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8, H.n, O->ld));
-    O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8, H.n, O->ld));
-    O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L, H.n, O->ld));
   }
   return O;
 }
@@ -278,6 +345,7 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
   W->dn_chk = alloc_bytes(W->col_bytes);
   W->dn_eq = alloc_bytes(W->col_bytes);
   W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * F.ntgt * 8));
+  W->absmax = static_cast<unsigned*>(alloc_bytes(16));
   return W;
 }
 
@@ -397,6 +465,28 @@ __global__ void scatter_kernel(PtrPack out, int prob0, const int64_t* __restrict
   for (int r = 0; r < n_rhs; ++r) dst[int64_t(r) * nk + ci] = TO(pot[int64_t(r) * ntgt + i]);
 }
 
+// Largest |x| over n4 float4 values, into *out as float bits (all values >= 0,
+// so unsigned order equals float order); *out must start at 0.
+__global__ void absmax_kernel(const float4* __restrict__ p, int64_t n4, unsigned* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += int64_t(gridDim.x) * blockDim.x) {
+    float4 v = p[i];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void absmax_kernel64(const double2* __restrict__ p, int64_t n2, unsigned* __restrict__ out) {
+  float m = 0.0f;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n2; i += int64_t(gridDim.x) * blockDim.x) {
+    double2 v = p[i];
+    m = fmaxf(m, float(fmax(fabs(v.x), fabs(v.y))));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
 __global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
        i += int64_t(gridDim.x) * blockDim.x)
@@ -421,7 +511,7 @@ struct P2PArgs {
   const int2* box_src;
   const int2* box_tgt;
   const double4* src64;
-  const typename V4<T>::type* tgt;
+  const double4* tgt64;
   const T* qs;
   int64_t nsrc;
   int n_rhs;
@@ -446,10 +536,7 @@ struct P2PCfg {
   // The batch size depends on T only, so every right-hand side sees the same
   // summation order whatever RC is (multi-RHS columns equal single runs bitwise).
   static constexpr int CAP = sizeof(T) == 4 ? 1024 : 512;
-  static constexpr int RED = NT * RC * 8;
-  static constexpr int SMEM = CAP * PB > RED ? CAP * PB : RED;
-  static constexpr int MAXSEG = 256;
-  static constexpr int NCH = 4;
+  static constexpr int BYTES = CAP * PB;
 };
 
 // (A -> B) frame change: shift = (c_A - c_B) / r_B, ratio = r_A / r_B.
@@ -463,18 +550,174 @@ __device__ inline double4 frame(int4 a, int4 b) {
   return g;
 }
 
-template <class T, int MODE, int RC, int TCH>
-__global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
-  using C = P2PCfg<T, RC>;
-  using V = typename V4<T>::type;
-  constexpr int NT = C::NT, SL = NT / TCH, CAP = C::CAP, MAXSEG = C::MAXSEG, NCH = C::NCH;
-  __shared__ __align__(16) unsigned char smem[C::SMEM];
-  __shared__ int s_pre[MAXSEG + 1];
-  __shared__ int s_id[MAXSEG];
-  __shared__ int s_kind[MAXSEG];
-  __shared__ double4 s_geo[MAXSEG];
+constexpr int kMaxSeg = 256, kNch = 4;
+
+struct SegTable {
+  int pre[kMaxSeg + 1];
+  int id[kMaxSeg];
+  int kind[kMaxSeg];
+  double4 geo[kMaxSeg];
+};
+
+// Source segment si of work item wi (target box B) for the given mode.
+template <class T, int MODE>
+__device__ inline void segment_info(const P2PArgs<T>& a, int wi, int B, int4 gB, int nU, int si,
+                                    int& kind, int& id, int& size, double4& g) {
+  if (MODE == MODE_P2M) {
+    int2 sr = a.box_src[B];
+    kind = SEG_POINTS;
+    id = sr.x;
+    size = sr.y - sr.x;
+    g = make_double4(0.0, 0.0, 0.0, 1.0);
+  } else if (si < nU) {
+    int A = a.l1_items[a.l1_off[wi] + si];
+    int2 sr = a.box_src[A];
+    kind = SEG_POINTS;
+    id = sr.x;
+    size = sr.y - sr.x;
+    g = frame(a.box_geo[A], gB);
+  } else if (MODE == MODE_LEAF && si < nU + (a.l2_off[wi + 1] - a.l2_off[wi])) {
+    int A = a.l2_items[a.l2_off[wi] + (si - nU)];
+    kind = SEG_UP_EQUIV;
+    id = A;
+    size = a.n;
+    g = frame(a.box_geo[A], gB);
+    g.w *= kRin;
+  } else {
+    kind = SEG_DN_EQUIV;
+    id = B;
+    size = a.n;
+    g = make_double4(0.0, 0.0, 0.0, kRout);
+  }
+}
+
+// Accumulates the sources of segments [s0, s1) into acc, computing pair terms
+// in precision U (staging in LDS, FP32/FP64 partials folded into FP64).
+template <class U, class T, int MODE, int RC, int TCH>
+__device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st, int wi, int B,
+                          int4 gB, int nU, int s0, int s1, int rhs0, const double (&tx)[kNch],
+                          const double (&ty)[kNch], const double (&tz)[kNch], int nchunks,
+                          double (&acc)[kNch][RC]) {
+  using C = P2PCfg<U, RC>;
+  using V = typename V4<U>::type;
+  constexpr int NT = 256, SL = NT / TCH, CAP = C::CAP;
   V* s_pos = reinterpret_cast<V*>(smem);
-  T* s_q = reinterpret_cast<T*>(smem + CAP * sizeof(V));
+  U* s_q = reinterpret_cast<U*>(smem + CAP * sizeof(V));
+  const int tid = threadIdx.x, sl = tid / TCH;
+  U ux[kNch], uy[kNch], uz[kNch];
+#pragma unroll
+  for (int c = 0; c < kNch; ++c) {
+    ux[c] = U(tx[c]);
+    uy[c] = U(ty[c]);
+    uz[c] = U(tz[c]);
+  }
+  for (int sw = s0; sw < s1; sw += kMaxSeg) {
+    const int nw = min(kMaxSeg, s1 - sw);
+    __syncthreads();
+    if (tid < nw) {
+      int kind, id, size;
+      double4 g;
+      segment_info<T, MODE>(a, wi, B, gB, nU, sw + tid, kind, id, size, g);
+      st.kind[tid] = kind;
+      st.id[tid] = id;
+      st.geo[tid] = g;
+      st.pre[tid + 1] = size;
+    }
+    if (tid == 0) st.pre[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < nw; off <<= 1) {
+      int v = (tid < nw && tid >= off) ? st.pre[tid + 1 - off] : 0;
+      __syncthreads();
+      if (tid < nw) st.pre[tid + 1] += v;
+      __syncthreads();
+    }
+    const int total = st.pre[nw];
+    for (int b0 = 0; b0 < total; b0 += CAP) {
+      const int nb = min(CAP, total - b0);
+      for (int j = tid; j < nb; j += NT) {
+        const int gidx = b0 + j;
+        int lo = 0, hi = nw - 1;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (st.pre[mid] <= gidx) lo = mid;
+          else hi = mid - 1;
+        }
+        const int local = gidx - st.pre[lo];
+        const int kind = st.kind[lo];
+        const double4 g = st.geo[lo];
+        double px, py, pz;
+        if (kind == SEG_POINTS) {
+          const int64_t pi = int64_t(st.id[lo]) + local;
+          double4 p = a.src64[pi];
+          px = g.x + g.w * p.x;
+          py = g.y + g.w * p.y;
+          pz = g.z + g.w * p.z;
+#pragma unroll
+          for (int r = 0; r < RC; ++r) {
+            int rr = rhs0 + r;
+            s_q[r * CAP + j] = rr < a.n_rhs ? U(a.qs[int64_t(rr) * a.nsrc + pi]) : U(0);
+          }
+        } else {
+          double4 s = a.surf[local];
+          px = g.x + g.w * s.x;
+          py = g.y + g.w * s.y;
+          pz = g.z + g.w * s.z;
+          const T* dens = kind == SEG_UP_EQUIV ? a.up_eq : a.dn_eq;
+          const int64_t col0 = int64_t(st.id[lo]) * a.n_rhs;
+#pragma unroll
+          for (int r = 0; r < RC; ++r) {
+            int rr = rhs0 + r;
+            s_q[r * CAP + j] = rr < a.n_rhs ? U(dens[(col0 + rr) * a.ld + local]) : U(0);
+          }
+        }
+        V v;
+        v.x = U(px);
+        v.y = U(py);
+        v.z = U(pz);
+        v.w = U(0);
+        s_pos[j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < kNch; ++c) {
+        if (c < nchunks) {
+          U part[RC];
+#pragma unroll
+          for (int r = 0; r < RC; ++r) part[r] = U(0);
+          const U x = ux[c], y = uy[c], z = uz[c];
+          for (int j = sl; j < nb; j += SL) {
+            V s = s_pos[j];
+            U dx = x - s.x, dy = y - s.y, dz = z - s.z;
+            U ri = rinv(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+            for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
+          }
+#pragma unroll
+          for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --- P2P-shaped operators -------------------------------------------------
+// One block per target box.  Targets are particles (LEAF) or surface points
+// (P2M: upward check, P2L: downward check); sources are "segments": the
+// particles of a leaf, or the equivalent surface of a box with its density.
+// Every source is moved into the target box's frame once, while it is staged
+// into LDS; targets are split into chunks of TCH lanes and the 256/TCH lane
+// groups stride over the staged sources, then reduce in FP64.  Particle
+// segments are computed in T, equivalent-surface segments (L2P, M2P) in TF:
+// FP64 at high order, where the equivalent densities cancel strongly.
+template <class T, class TF, int MODE, int RC, int TCH>
+__global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
+  constexpr int NT = 256, SL = NT / TCH;
+  constexpr int SMEM0 = P2PCfg<T, RC>::BYTES > P2PCfg<TF, RC>::BYTES ? P2PCfg<T, RC>::BYTES
+                                                                     : P2PCfg<TF, RC>::BYTES;
+  constexpr int RED = NT * RC * 8;
+  __shared__ __align__(16) unsigned char smem[SMEM0 > RED ? SMEM0 : RED];
+  __shared__ SegTable st;
   double* s_red = reinterpret_cast<double*>(smem);
 
   const int tid = threadIdx.x, ti = tid % TCH, sl = tid / TCH;
@@ -483,173 +726,61 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
   const int rhs0 = blockIdx.y * RC;
   const int4 gB = a.box_geo[B];
 
-  int nU = 0, nW = 0, nseg = 0;
+  int nU = 0, nseg = 0, nnear = 0;
   if (MODE == MODE_P2M) {
-    nseg = 1;
+    nseg = nnear = 1;
   } else if (MODE == MODE_P2L) {
     nU = a.l1_off[wi + 1] - a.l1_off[wi];
-    nseg = nU;
+    nseg = nnear = nU;
   } else {
     nU = a.l1_off[wi + 1] - a.l1_off[wi];
-    nW = a.l2_off[wi + 1] - a.l2_off[wi];
+    const int nW = a.l2_off[wi + 1] - a.l2_off[wi];
+    nnear = nU;
     nseg = nU + nW + (gB.w >= 2 ? 1 : 0);
   }
   int nt, tbase = 0;
-  T trad = T(0);
+  double trad = 0.0;
   if (MODE == MODE_LEAF) {
     int2 tr = a.box_tgt[B];
     tbase = tr.x;
     nt = tr.y - tr.x;
   } else {
     nt = a.n;
-    trad = T(MODE == MODE_P2M ? kRout : kRin);
+    trad = MODE == MODE_P2M ? kRout : kRin;
   }
 
-  for (int t0 = 0; t0 < nt; t0 += TCH * NCH) {
-    T tx[NCH], ty[NCH], tz[NCH];
-    double acc[NCH][RC];
+  for (int t0 = 0; t0 < nt; t0 += TCH * kNch) {
+    double tx[kNch], ty[kNch], tz[kNch];
+    double acc[kNch][RC];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < kNch; ++c) {
       int t = t0 + c * TCH + ti;
-      tx[c] = ty[c] = tz[c] = T(0);
+      tx[c] = ty[c] = tz[c] = 0.0;
       if (t < nt) {
         if (MODE == MODE_LEAF) {
-          V p = a.tgt[tbase + t];
+          double4 p = a.tgt64[tbase + t];
           tx[c] = p.x;
           ty[c] = p.y;
           tz[c] = p.z;
         } else {
           double4 s = a.surf[t];
-          tx[c] = T(double(trad) * s.x);
-          ty[c] = T(double(trad) * s.y);
-          tz[c] = T(double(trad) * s.z);
+          tx[c] = trad * s.x;
+          ty[c] = trad * s.y;
+          tz[c] = trad * s.z;
         }
       }
 #pragma unroll
       for (int r = 0; r < RC; ++r) acc[c][r] = 0.0;
     }
-    int nchunks = (min(nt - t0, TCH * NCH) + TCH - 1) / TCH;
-
-    for (int sw = 0; sw < nseg; sw += MAXSEG) {
-      const int nw = min(MAXSEG, nseg - sw);
-      __syncthreads();
-      if (tid < nw) {
-        const int si = sw + tid;
-        int kind, id, size;
-        double4 g;
-        if (MODE == MODE_P2M) {
-          int2 sr = a.box_src[B];
-          kind = SEG_POINTS;
-          id = sr.x;
-          size = sr.y - sr.x;
-          g = make_double4(0.0, 0.0, 0.0, 1.0);
-        } else if (si < nU) {
-          int A = a.l1_items[a.l1_off[wi] + si];
-          int2 sr = a.box_src[A];
-          kind = SEG_POINTS;
-          id = sr.x;
-          size = sr.y - sr.x;
-          g = frame(a.box_geo[A], gB);
-        } else if (si < nU + nW) {
-          int A = a.l2_items[a.l2_off[wi] + (si - nU)];
-          kind = SEG_UP_EQUIV;
-          id = A;
-          size = a.n;
-          g = frame(a.box_geo[A], gB);
-          g.w *= kRin;
-        } else {
-          kind = SEG_DN_EQUIV;
-          id = B;
-          size = a.n;
-          g = make_double4(0.0, 0.0, 0.0, kRout);
-        }
-        s_kind[tid] = kind;
-        s_id[tid] = id;
-        s_geo[tid] = g;
-        s_pre[tid + 1] = size;
-      }
-      if (tid == 0) s_pre[0] = 0;
-      __syncthreads();
-      for (int off = 1; off < nw; off <<= 1) {
-        int v = (tid < nw && tid >= off) ? s_pre[tid + 1 - off] : 0;
-        __syncthreads();
-        if (tid < nw) s_pre[tid + 1] += v;
-        __syncthreads();
-      }
-      const int total = s_pre[nw];
-
-      for (int b0 = 0; b0 < total; b0 += CAP) {
-        const int nb = min(CAP, total - b0);
-        for (int j = tid; j < nb; j += NT) {
-          const int gidx = b0 + j;
-          int lo = 0, hi = nw - 1;
-          while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (s_pre[mid] <= gidx) lo = mid;
-            else hi = mid - 1;
-          }
-          const int local = gidx - s_pre[lo];
-          const int kind = s_kind[lo];
-          const double4 g = s_geo[lo];
-          double px, py, pz;
-          if (kind == SEG_POINTS) {
-            const int64_t pi = int64_t(s_id[lo]) + local;
-            double4 p = a.src64[pi];
-            px = g.x + g.w * p.x;
-            py = g.y + g.w * p.y;
-            pz = g.z + g.w * p.z;
-#pragma unroll
-            for (int r = 0; r < RC; ++r) {
-              int rr = rhs0 + r;
-              s_q[r * CAP + j] = rr < a.n_rhs ? a.qs[int64_t(rr) * a.nsrc + pi] : T(0);
-            }
-          } else {
-            double4 s = a.surf[local];
-            px = g.x + g.w * s.x;
-            py = g.y + g.w * s.y;
-            pz = g.z + g.w * s.z;
-            const T* dens = kind == SEG_UP_EQUIV ? a.up_eq : a.dn_eq;
-            const int64_t col0 = int64_t(s_id[lo]) * a.n_rhs;
-#pragma unroll
-            for (int r = 0; r < RC; ++r) {
-              int rr = rhs0 + r;
-              s_q[r * CAP + j] = rr < a.n_rhs ? dens[(col0 + rr) * a.ld + local] : T(0);
-            }
-          }
-          V v;
-          v.x = T(px);
-          v.y = T(py);
-          v.z = T(pz);
-          v.w = T(0);
-          s_pos[j] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-          if (c < nchunks) {
-            T part[RC];
-#pragma unroll
-            for (int r = 0; r < RC; ++r) part[r] = T(0);
-            const T x = tx[c], y = ty[c], z = tz[c];
-            for (int j = sl; j < nb; j += SL) {
-              V s = s_pos[j];
-              T dx = x - s.x, dy = y - s.y, dz = z - s.z;
-              T ri = rinv(dx * dx + dy * dy + dz * dz);
-#pragma unroll
-              for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
-            }
-#pragma unroll
-            for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
-          }
-        }
-        __syncthreads();
-      }
-    }
+    const int nchunks = (min(nt - t0, TCH * kNch) + TCH - 1) / TCH;
+    p2p_phase<T, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks, acc);
+    if (nseg > nnear)
+      p2p_phase<TF, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz, nchunks, acc);
 
     // reduce the slices of each chunk and write
     const double rB = a.box_r[B];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
+    for (int c = 0; c < kNch; ++c) {
       if (c < nchunks) {
         __syncthreads();
 #pragma unroll
@@ -701,9 +832,11 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-enum { GM_F32 = 0, GM_F64 = 1, GM_BF3 = 2, GM_BF5 = 3 };
+enum { GM_F32 = 0, GM_F64 = 1, GM_BF3 = 2, GM_BF5 = 3, GM_H3 = 4 };
+
+
 
 template <int MODE> struct GT;
 template <> struct GT<GM_F32> {
@@ -731,6 +864,12 @@ template <> struct GT<GM_BF5> {
   static constexpr int KC = 32, NB = 3, SA = KC + 8;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
+template <> struct GT<GM_H3> {
+  using TA = _Float16;
+  using acc = f32x4;
+  static constexpr int KC = 32, NB = 2, SA = KC + 8;
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
 
 struct GemmArgs {
   const void* ops;      // FP32/FP64: [nop][ld][ld]; BF: high parts [nop][ld][ld]
@@ -743,6 +882,7 @@ struct GemmArgs {
   const int32_t* step_beg;
   const int32_t* step_op;
   const int32_t* step_src;
+  const unsigned* absmax;  // FP16 split: bits of max |input| (non-negative float)
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
@@ -752,7 +892,7 @@ struct GemmCfg {
   using G = GT<MODE>;
   using TA = typename G::TA;
   static constexpr int KC = G::KC, SA = G::SA, NB = G::NB, TC = 64 * CB;
-  static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5) ? 2 : 1;  // operator tables
+  static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3) ? 2 : 1;  // operator tables
   // per buffer: NA operator tiles [ROWS][SA] and NB column tiles [TC][SA] of TA
   static constexpr int A_ELEMS = NA * kROWS * SA, B_ELEMS = NB * TC * SA;
   static constexpr int BUF_BYTES = (A_ELEMS + B_ELEMS) * int(sizeof(TA));
@@ -765,34 +905,59 @@ struct GemmCfg {
   static constexpr int B_PER_T = (B_UNITS + 255) / 256;
 };
 
-template <class T>
-__device__ inline void split_store(__bf16* dst_h, __bf16* dst_m, __bf16* dst_l, int nb, const T* v, int cnt) {
-  for (int i = 0; i < cnt; ++i) {
-    float x = float(v[i]);
-    __bf16 h = __bf16(x);
-    float r = x - float(h);
-    __bf16 m = __bf16(r);
-    if (nb == 2) {
-      dst_h[i] = h;
-      dst_l[i] = m;
-    } else {
-      float r2 = r - float(m);
-      dst_h[i] = h;
-      dst_m[i] = m;
-      dst_l[i] = __bf16(r2);
-    }
+// Splits 4 (or 2) inputs x*scale into nb low-precision parts, written as one
+// 8-byte (4-byte) store per part.
+template <class H, int NB, class T, int CNT>
+__device__ inline void split_store(H* dst_h, H* dst_m, H* dst_l, const T* v, float scale) {
+  H h[CNT], m[CNT], l[CNT];
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    float x = float(v[i]) * scale;
+    h[i] = H(x);
+    float r = x - float(h[i]);
+    m[i] = H(r);
+    if constexpr (NB == 3) l[i] = H(r - float(m[i]));
+  }
+  typedef H vec __attribute__((ext_vector_type(CNT)));
+  vec vh, vm, vl;
+#pragma unroll
+  for (int i = 0; i < CNT; ++i) {
+    vh[i] = h[i];
+    vm[i] = m[i];
+    if constexpr (NB == 3) vl[i] = l[i];
+  }
+  *reinterpret_cast<vec*>(dst_h) = vh;
+  if constexpr (NB == 2) {
+    *reinterpret_cast<vec*>(dst_l) = vm;
+  } else {
+    *reinterpret_cast<vec*>(dst_m) = vm;
+    *reinterpret_cast<vec*>(dst_l) = vl;
   }
 }
 
-template <int MODE, class TI, class TO, int CB>
-__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
+// TAG separates the M2L launches into their own symbols: 1 = M2L, 2 = M2L
+// with FP32 sums moved into FP64 registers after every operator step.
+template <int MODE, class TI, class TO, int CB, int TAG>
+__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   using Cfg = GemmCfg<MODE, TI, TO, CB>;
   using G = GT<MODE>;
   using TA = typename Cfg::TA;
   using ACC = typename G::acc;
   constexpr int KC = Cfg::KC, SA = Cfg::SA, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
-  constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5);
+  constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
   __shared__ __align__(16) unsigned char smem[2 * Cfg::BUF_BYTES];
+  // FP16 split: exact power-of-two scaling of the densities into range
+  float in_scale = 1.0f, out_scale = 1.0f;
+  if constexpr (MODE == GM_H3) {
+    const float mx = __uint_as_float(*a.absmax);
+    int e = 0;
+    if (mx > 0.0f) {
+      (void)frexpf(mx, &e);  // mx in [2^(e-1), 2^e)
+      e = 14 - e;
+    }
+    in_scale = ldexpf(1.0f, e);
+    out_scale = ldexpf(1.0f, -e - kF16OpExp);
+  }
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int tile = blockIdx.x;
@@ -811,6 +976,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
     for (int c = 0; c < CB; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][c][v] = 0;
+  // TAG 2: after every operator step the FP32 sums are moved into FP64
+  // registers, so FP32 rounding spans one step (one n x n product) only
+  constexpr bool FLUSH = TAG == 2 && MODE != GM_F64;
+  f64x4 acc64[FLUSH ? kRB : 1][FLUSH ? CB : 1];
+  if constexpr (FLUSH) {
+#pragma unroll
+    for (int i = 0; i < kRB; ++i)
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[i][c][v] = 0.0;
+  }
 
   uint4 ra[Cfg::A_PER_T], rb[Cfg::B_PER_T];
   int64_t bcol[Cfg::B_PER_T];
@@ -882,10 +1059,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
         const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
         const TI* vals = reinterpret_cast<const TI*>(&rb[j]);
         if constexpr (BF) {
-          __bf16* h = Bs + s * SA + part * EPU;
-          __bf16* m = h + TC * SA;
-          __bf16* l = h + (NB - 1) * TC * SA;
-          split_store(h, m, l, NB, vals, EPU);
+          TA* h = Bs + s * SA + part * EPU;
+          TA* m = h + TC * SA;
+          TA* l = h + (NB - 1) * TC * SA;
+          split_store<TA, NB, TI, EPU>(h, m, l, vals, in_scale);
         } else {
           TA* d = Bs + s * SA + part * EPU;
 #pragma unroll
@@ -929,29 +1106,32 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
                 acc[i][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv[c][e], acc[i][c], 0, 0, 0);
             }
     } else {
-      bf16x8 bh[CB], bm[CB], bl[CB];
+      using vec8 = typename std::conditional<MODE == GM_H3, f16x8, bf16x8>::type;
+      auto mma = [](vec8 x, vec8 y, f32x4 c) {
+        if constexpr (MODE == GM_H3) return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+        else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+      };
+      vec8 bh[CB], bm[CB], bl[CB];
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
         const int col = wave * 16 * CB + c * 16 + r16;
-        bh[c] = *reinterpret_cast<const bf16x8*>(Bs + col * SA + g * 8);
-        bl[c] = *reinterpret_cast<const bf16x8*>(Bs + (NB - 1) * TC * SA + col * SA + g * 8);
-        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const bf16x8*>(Bs + TC * SA + col * SA + g * 8);
+        bh[c] = *reinterpret_cast<const vec8*>(Bs + col * SA + g * 8);
+        bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * TC * SA + col * SA + g * 8);
+        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + TC * SA + col * SA + g * 8);
       }
 #pragma unroll
       for (int i = 0; i < kRB; ++i) {
-        {
-          const bf16x8 ah = *reinterpret_cast<const bf16x8*>(As + (i * 16 + r16) * SA + g * 8);
-          const bf16x8 al = *reinterpret_cast<const bf16x8*>(As + kROWS * SA + (i * 16 + r16) * SA + g * 8);
+        const vec8 ah = *reinterpret_cast<const vec8*>(As + (i * 16 + r16) * SA + g * 8);
+        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * SA + (i * 16 + r16) * SA + g * 8);
 #pragma unroll
-          for (int c = 0; c < CB; ++c) {
-            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[c], acc[i][c], 0, 0, 0);
-            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[c], acc[i][c], 0, 0, 0);
-            if constexpr (NB == 3) {
-              acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[c], acc[i][c], 0, 0, 0);
-              acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bm[c], acc[i][c], 0, 0, 0);
-            }
-            acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[c], acc[i][c], 0, 0, 0);
+        for (int c = 0; c < CB; ++c) {
+          acc[i][c] = mma(ah, bh[c], acc[i][c]);
+          acc[i][c] = mma(al, bh[c], acc[i][c]);
+          if constexpr (NB == 3) {
+            acc[i][c] = mma(ah, bm[c], acc[i][c]);
+            acc[i][c] = mma(al, bm[c], acc[i][c]);
           }
+          acc[i][c] = mma(ah, bl[c], acc[i][c]);
         }
       }
     }
@@ -965,6 +1145,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
       const int buf = ch & 1;
       if (ch + 1 < nchunks) load_regs(ch + 1);
       compute(buf);
+      if constexpr (FLUSH) {
+        if ((ch + 1) % kcs == 0) {
+#pragma unroll
+          for (int i = 0; i < kRB; ++i)
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                acc64[i][c][v] += double(acc[i][c][v]);
+                acc[i][c][v] = 0;
+              }
+        }
+      }
       if (ch + 1 < nchunks) store_lds(buf ^ 1);
       __syncthreads();
     }
@@ -984,8 +1177,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int row = row0 + i * 16 + G::row(lane, v);
-              using TAcc = decltype(acc[0][0][0] + 0);
-              TAcc val = acc[i][c][v];
+              // summed in the wider of the accumulator and output types
+              using TAcc = typename std::conditional<(sizeof(TO) > sizeof(acc[0][0][0])), TO,
+                                                     decltype(acc[0][0][0] + 0)>::type;
+              TAcc val = TAcc(acc[i][c][v]);
+              if constexpr (FLUSH) val = TAcc(acc64[i][c][v] + double(acc[i][c][v]));
+              if constexpr (MODE == GM_H3) val *= TAcc(out_scale);
               if (a.accumulate) val += TAcc(o[row]);
               o[row] = TO(val);
             }
@@ -1000,43 +1197,57 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs a) {
 // pipeline
 // ------------------------------------------------------------------------
 
-template <int MODE, class TI, class TO>
+template <int MODE, class TI, class TO, int TAG = 0>
 static void run_gemm(const DevPlan& P, const void* ops, const void* ops_lo, int64_t op_stride,
                      int ld, int n_rhs, const TI* in, TO* out, bool accumulate, hipStream_t s,
-                     PhaseScope& ps) {
+                     PhaseScope& ps, const unsigned* absmax = nullptr) {
   if (P.ntile == 0) return;
   const int ncols = P.TB * n_rhs;
   if (ncols > 128) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
   GemmArgs g{ops, ops_lo, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
-             P.tile_cols, P.step_beg, P.step_op, P.step_src};
+             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
   if (ncols > 64)
-    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG>), grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG>), grid, dim3(256), 0, s, g);
   LAUNCHCHECK("gemm_kernel");
   ps.launches++;
 }
 
-template <class T, int MODE, int RC, int TCH>
+template <class T, class TF, int MODE, int RC, int TCH>
 static void run_p2p(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
   if (nwork == 0) return;
   dim3 grid(nwork, (n_rhs + RC - 1) / RC);
-  hipLaunchKernelGGL((p2p_kernel<T, MODE, RC, TCH>), grid, dim3(256), 0, s, args);
+  hipLaunchKernelGGL((p2p_kernel<T, TF, MODE, RC, TCH>), grid, dim3(256), 0, s, args);
   LAUNCHCHECK("p2p_kernel");
   ps.launches++;
 }
 
+// Equivalent-surface terms (L2P, M2P) can run in FP64 at high order: the
+// equivalent densities cancel more strongly as p grows (the pseudo-inverse
+// keeps singular values down to rcond), so FP32 kernel values limit the far
+// field to ~1e-5 at p = 10.
+static int g_far_fp64_min_p = 10;
+void set_far_fp64_min_p(int p) { g_far_fp64_min_p = p; }
+
 template <class T, int MODE, int TCH>
-static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
-  if (n_rhs == 1) run_p2p<T, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
-  else run_p2p<T, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
+static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64, hipStream_t s,
+                       PhaseScope& ps) {
+  if (far64) {
+    if (n_rhs == 1) run_p2p<T, double, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
+    else run_p2p<T, double, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
+  } else {
+    if (n_rhs == 1) run_p2p<T, T, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
+    else run_p2p<T, T, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
+  }
 }
 
 template <class T, class TIO>
 static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* charges,
-                     void* const* potentials, int n_rhs, kifmm_precision prec, hipStream_t s) {
+                     void* const* potentials, int n_rhs, kifmm_precision prec, bool check_form,
+                     hipStream_t s) {
   constexpr int GF = sizeof(T) == 8 ? GM_F64 : GM_F32;
   const int ld = F.ld;
   const int64_t nn = int64_t(ld) * ld;
@@ -1047,15 +1258,12 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   T* dn_eq = static_cast<T*>(W.dn_eq);
   const T* m2m = nullptr;
   const T* l2l = nullptr;
-  const T* m2l = nullptr;
   if constexpr (sizeof(T) == 8) {
     m2m = O.m2m64;
     l2l = O.l2l64;
-    m2l = O.m2l64;
   } else {
     m2m = O.m2m32;
     l2l = O.l2l32;
-    m2l = O.m2l32;
   }
 
   {
@@ -1077,8 +1285,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.box_src = F.box_src;
   base.box_tgt = F.box_tgt;
   base.src64 = F.src64;
-  if constexpr (sizeof(T) == 8) base.tgt = F.tgt64;
-  else base.tgt = F.tgt32;
+  base.tgt64 = F.tgt64;
   base.qs = qs;
   base.nsrc = F.nsrc;
   base.n_rhs = n_rhs;
@@ -1094,7 +1301,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     P2PArgs<T> a = base;
     a.work = F.p2m_boxes;
     a.out_col = up_chk;
-    run_p2p_rc<T, MODE_P2M, 64>(a, F.n_p2m, n_rhs, s, ps);
+    run_p2p_rc<T, MODE_P2M, 64>(a, F.n_p2m, n_rhs, false, s, ps);
   }
   for (int l = F.depth; l >= 2; --l) {
     {
@@ -1117,19 +1324,48 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.l1_off = F.x_off;
     a.l1_items = F.x_items;
     a.out_col = dn_chk;
-    run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, s, ps);
+    run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, false, s, ps);
   }
   {
     PhaseScope ps(PH_M2L, s);
-    if constexpr (sizeof(T) == 8) {
-      run_gemm<GM_F64, T, T>(F.m2l, m2l, nullptr, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
-    } else {
-      if (prec == KIFMM_M2L_BF16X3)
-        run_gemm<GM_BF3, T, T>(F.m2l, O.m2l_bh, O.m2l_bl, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
-      else if (prec == KIFMM_M2L_BF16X5)
-        run_gemm<GM_BF5, T, T>(F.m2l, O.m2l_bh, O.m2l_bl, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+    // operand of M2L: upward densities, or (check form) upward check potentials
+    const T* m2l_in = check_form ? up_chk : up_eq;
+    auto scale16 = [&]() {
+      hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint4*>(W.absmax), int64_t(1));
+      LAUNCHCHECK("zero_kernel");
+      if constexpr (sizeof(T) == 8)
+        hipLaunchKernelGGL(absmax_kernel64, dim3(1024), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(m2l_in), int64_t(W.col_bytes / 16), W.absmax);
       else
-        run_gemm<GM_F32, T, T>(F.m2l, m2l, nullptr, nn, ld, n_rhs, up_eq, dn_chk, true, s, ps);
+        hipLaunchKernelGGL(absmax_kernel, dim3(1024), dim3(256), 0, s,
+                           reinterpret_cast<const float4*>(m2l_in), int64_t(W.col_bytes / 16), W.absmax);
+      LAUNCHCHECK("absmax_kernel");
+      ps.launches += 2;
+    };
+    const bool fp64_sum = O.p >= g_m2l_fp64_sum_min_p;
+    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const void* opb, const T* in,
+                            const unsigned* amax) {
+      constexpr int MODE = decltype(mode_tag)::value;
+      if (fp64_sum)
+        run_gemm<MODE, T, T, 2>(F.m2l, opa, opb, nn, ld, n_rhs, in, dn_chk, true, s, ps, amax);
+      else
+        run_gemm<MODE, T, T, 1>(F.m2l, opa, opb, nn, ld, n_rhs, in, dn_chk, true, s, ps, amax);
+    };
+    const void* op32 = check_form ? static_cast<const void*>(O.m2lc32) : static_cast<const void*>(O.m2l32);
+    const void* oph = check_form ? O.m2lc_hh : O.m2l_hh;
+    const void* opl = check_form ? O.m2lc_hl : O.m2l_hl;
+    if (prec == KIFMM_FP64) {
+      run_gemm<GM_F64, T, T, 1>(F.m2l, O.m2l64, nullptr, nn, ld, n_rhs, m2l_in, dn_chk, true, s, ps);
+    } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
+      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, nullptr, m2l_in, nullptr);
+    } else if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) {
+      scale16();
+      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, opl, m2l_in, W.absmax);
+    } else if constexpr (sizeof(T) == 4) {
+      if (prec == KIFMM_M2L_BF16X3)
+        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_bh, O.m2l_bl, up_eq, nullptr);
+      else
+        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_bh, O.m2l_bl, up_eq, nullptr);
     }
   }
   for (int l = 2; l <= F.depth; ++l) {
@@ -1150,7 +1386,8 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.l1_items = F.u_items;
     a.l2_off = F.w_off;
     a.l2_items = F.w_items;
-    run_p2p_rc<T, MODE_LEAF, 32>(a, F.n_leaf, n_rhs, s, ps);
+    const bool far64 = sizeof(T) == 4 && O.p >= g_far_fp64_min_p;
+    run_p2p_rc<T, MODE_LEAF, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
   }
   {
     PhaseScope ps(PH_SCATTER, s);
@@ -1177,18 +1414,26 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
     st.forest = upload_forest(*st.host, hops.n);
     st.device = dev;
   }
-  const bool fp64 = prec == KIFMM_FP64;
-  DevOps* O = ops_for_device(oc, hops, dev, fp64, prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5);
+  const bool fp64 = prec == KIFMM_FP64 || prec == KIFMM_FP64_M2L_FP32 || prec == KIFMM_FP64_M2L_F16X3;
+  OpsNeed need;
+  need.bulk64 = fp64;
+  need.m2l64 = prec == KIFMM_FP64;
+  need.m2l32 = prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32;
+  need.bf16 = prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5;
+  need.f16 = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3;
+  // folded check form for the FP32 / FP16 M2L operands at high order
+  need.check_form = (need.m2l32 || need.f16) && hops.p >= g_m2l_check_min_p;
+  DevOps* O = ops_for_device(oc, hops, dev, need);
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
   DevWork* W = work_for(F, fp64, n_rhs);
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (fp64) {
-    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, s);
-    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, s);
+    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
   } else {
-    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, s);
-    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, s);
+    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
   }
 }
 

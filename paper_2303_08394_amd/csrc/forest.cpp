@@ -114,8 +114,6 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
     for (int64_t i = 0; i < T.nsrc; ++i) F.src_perm[so + i] = int32_t(T.sperm[i]);
     for (int64_t i = 0; i < T.ntgt; ++i) F.tgt_perm[to + i] = int32_t(T.tperm[i]);
   }
-  F.src_f32.assign(F.src_f64.begin(), F.src_f64.end());
-  F.tgt_f32.assign(F.tgt_f64.begin(), F.tgt_f64.end());
 
   auto nsrc_of = [&](int32_t g) { return F.box_src[2 * size_t(g) + 1] - F.box_src[2 * size_t(g)]; };
   auto ntgt_of = [&](int32_t g) { return F.box_tgt[2 * size_t(g) + 1] - F.box_tgt[2 * size_t(g)]; };
@@ -231,6 +229,22 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
         }
       }
     }
+    // Targets of one (level, octant) class are ordered by the set of offsets
+    // of their V list (then Morton order), so that a tile holds boxes with the
+    // same or similar offsets and few steps run with empty columns; boxes
+    // away from the domain boundary all share the full set.
+    std::vector<std::vector<uint64_t>> mask(NB);
+    for (int32_t g : tg) {
+      mask[g].assign((kNumM2L + 63) / 64, 0);
+      for (auto& e : vl[g]) mask[g][e.first >> 6] |= uint64_t(1) << (e.first & 63);
+    }
+    std::stable_sort(tg.begin(), tg.end(), [&](int32_t x, int32_t y) {
+      int64_t kx = int64_t(F.box_geo[4 * size_t(x) + 3]) * 8 + F.box_octant[x];
+      int64_t ky = int64_t(F.box_geo[4 * size_t(y) + 3]) * 8 + F.box_octant[y];
+      if (kx != ky) return kx < ky;
+      if (mask[x] != mask[y]) return mask[x] > mask[y];
+      return x < y;
+    });
     auto tiles = group_tiles(tg, TBm, [&](int32_t g) {
       return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g];
     });

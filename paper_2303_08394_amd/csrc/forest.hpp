@@ -41,7 +41,6 @@ struct HostForest {
   std::vector<int32_t> box_octant, box_leaf;
   // points, sorted, coordinates relative to their leaf: (x - c) / r, w = 0
   std::vector<double> src_f64, tgt_f64;  // [n][4]
-  std::vector<float> src_f32, tgt_f32;   // [n][4]
   std::vector<int32_t> src_perm, tgt_perm;  // sorted -> caller index (within problem)
   // leaf work lists
   std::vector<int32_t> p2m_boxes;   // leaves at level >= 2 holding sources

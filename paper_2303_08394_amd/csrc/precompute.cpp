@@ -130,6 +130,26 @@ std::vector<double> pinv_truncated(const double* a, int n, double rcond, int* ra
   return P;
 }
 
+std::vector<double> m2l_check_form(const HostOps& O) {
+  const int n = O.n;
+  const size_t nn = size_t(n) * n;
+  std::vector<double> out(size_t(kNumM2L) * nn, 0.0);
+  parallel_for(kNumM2L, [&](int64_t b, int64_t e) {
+    for (int64_t k = b; k < e; ++k) {
+      const double* A = &O.m2l[size_t(k) * nn];
+      double* C = &out[size_t(k) * nn];
+      for (int i = 0; i < n; ++i)
+        for (int l = 0; l < n; ++l) {
+          const double a = A[size_t(i) * n + l];
+          const double* Br = &O.uc2e[size_t(l) * n];
+          double* Cr = &C[size_t(i) * n];
+          for (int j = 0; j < n; ++j) Cr[j] += a * Br[j];
+        }
+    }
+  }, 1);
+  return out;
+}
+
 HostOps* build_host_ops(int p, double rcond) {
   if (p < 2 || p > 16) raise(KIFMM_EINVAL, "precompute_operators: p must be in [2, 16]");
   if (!(rcond > 0.0 && rcond < 1.0)) raise(KIFMM_EINVAL, "precompute_operators: rcond must be in (0, 1)");

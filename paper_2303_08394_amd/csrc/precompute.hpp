@@ -32,6 +32,11 @@ struct HostOps {
 
 HostOps* build_host_ops(int p, double rcond);
 
+// M2L folded with the upward solve: m2l[o] * uc2e for every offset, FP64,
+// [316][n][n].  Maps a source box's scaled upward check potential straight
+// to the target's scaled downward check potential.
+std::vector<double> m2l_check_form(const HostOps& ops);
+
 // One-sided Jacobi SVD of the square row-major matrix a [n][n]:
 // a = U diag(s) V^T; outputs U, V row-major [n][n], s descending.
 void jacobi_svd(const double* a, int n, std::vector<double>& U, std::vector<double>& s,

@@ -14,8 +14,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkifmm.so")
 
-FP64, FP32, M2L_BF16X3, M2L_BF16X5 = 0, 1, 2, 3
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": M2L_BF16X3, "bf16x5": M2L_BF16X5}
+FP64, FP32, M2L_BF16X3, M2L_BF16X5, M2L_F16X3, FP64_M2L_FP32, FP64_M2L_F16X3 = range(7)
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": M2L_BF16X3, "bf16x5": M2L_BF16X5,
+              "f16x3": M2L_F16X3, "fp64+m2l_fp32": FP64_M2L_FP32, "fp64+m2l_f16x3": FP64_M2L_F16X3}
 LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED"}
 

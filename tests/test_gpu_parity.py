@@ -21,7 +21,8 @@ from paper_2303_08394_amd import kifmm as K  # noqa: E402
 
 CUBE = dict(center=(0.5, 0.5, 0.5), halfwidth=0.5)
 TOL64, TOL32 = 1e-8, 1e-5
-TOL = {"fp64": TOL64, "fp32": TOL32, "bf16x3": TOL32, "bf16x5": TOL32}
+TOL = {"fp64": TOL64, "fp32": TOL32, "bf16x3": TOL32, "bf16x5": TOL32, "f16x3": TOL32,
+       "fp64+m2l_fp32": TOL32, "fp64+m2l_f16x3": TOL32}
 DEV = "cuda:0"
 
 
@@ -72,7 +73,8 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16x5"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "bf16x5", "f16x3", "fp64+m2l_fp32",
+                                       "fp64+m2l_f16x3"])
 def test_parity_vs_oracle(name, precision):
     x, q, tgt, p, kw = _case(name)
     want = oracle(name, x, q, tgt, p, **kw)
@@ -152,3 +154,22 @@ def test_evaluate_simple_matches_direct():
     x, q = I.sphere_surface(4000, seed=17)
     got = K.evaluate_simple(x, q[0], x, 6)
     assert rel(got, direct.direct(x, q[0], x)) < 1e-5
+
+
+@pytest.mark.parametrize("precision", ["fp32", "f16x3", "fp64+m2l_f16x3"])
+def test_check_form_m2l(precision):
+    """M2L on upward check potentials with operators folded with UC2E (the
+    high-order form), forced at low order, against the oracle."""
+    name = "uniform20k_d3_p6"
+    x, q, tgt, p, kw = _case(name)
+    want = oracle(name, x, q, tgt, p, **kw)
+    K.set_tuning("m2l_check_min_p", 2)
+    try:
+        tree = K.Tree(x, tgt, **kw)
+        got = gpu_eval(tree, p, q, precision)
+    finally:
+        K.set_tuning("m2l_check_min_p", 10)
+        _ops.clear()
+    e = rel(got, want)
+    print(f"check-form {precision} rel L2 vs oracle = {e:.3e}")
+    assert e < TOL32
