@@ -135,6 +135,7 @@ def main():
                     choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16x3", "bf16x5", "f16x3", "fp64", "fp64+m2l_fp32", "fp64+m2l_f16x3"])
     ap.add_argument("--no-fp64-leg", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-sample", type=int, default=200)
     ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128)")
@@ -189,6 +190,24 @@ def main():
         else:
             K.evaluate(tree, ops, qs[0], precision=precision, out=outs[0])
 
+    def run_graph(precision, steps, warmup):
+        """Timed replays of the captured evaluation on a non-default stream."""
+        stream = torch.cuda.Stream()
+        if batch:
+            outs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs]
+        else:
+            outs = [torch.empty((n_rhs, n), dtype=torch.float64, device=dev)]
+        with torch.cuda.stream(stream):
+            for _ in range(max(1, warmup)):
+                evaluate_all(precision, outs)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for _ in range(steps):
+                evaluate_all(precision, outs)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+        return (tb - ta) / steps
+
     def run(precision, steps, warmup):
         if batch:
             outs = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs]
@@ -213,10 +232,13 @@ def main():
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
     precision = args.precision or DEFAULT_PRECISION[args.config]
-    res, t_step, phases = run(precision, args.steps, args.warmup)
-    result = {}
+    res, t_eager, phases = run(precision, args.steps, args.warmup)
+    result = {"eager_profiled_ms_per_step": t_eager * 1e3}
+    t_step = run_graph(precision, args.steps, args.warmup) if not args.no_graph else t_eager
     if not args.no_fp64_leg and precision != "fp64" and args.config != "multi_rhs_1m":
         ref, t64, ph64 = run("fp64", max(2, args.steps // 4), 1)
+        if not args.no_graph:
+            t64 = run_graph("fp64", max(2, args.steps // 4), 1)
         result["fp64_ms_per_step"] = t64 * 1e3
         result["speedup_vs_fp64"] = t64 / t_step
         result["rel_l2_vs_fp64_gpu"] = rel(np.concatenate([r.ravel() for r in res]),

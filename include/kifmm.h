@@ -142,7 +142,8 @@ kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out,
                               int64_t n_out);
 int32_t kifmm_ops_n(const kifmm_ops* ops); /* surface points n, or -1 */
 
-/* Evaluate the potentials.  charges: DEVICE [n_rhs][n_src] (caller order),
+/* Evaluate the potentials (one hipGraph replay on a non-default stream, see
+ * the "graph" tuning key).  charges: DEVICE [n_rhs][n_src] (caller order),
  * potentials: DEVICE [n_rhs][n_tgt] (caller order), both FP64 if
  * io_fp64 != 0, else FP32.  n_rhs >= 1.  Runs asynchronously on hip_stream
  * (a hipStream_t; NULL = the default stream); inputs must stay valid and
@@ -205,6 +206,10 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     act on upward check potentials with the operators
  *                     folded with UC2E (M2L_o * UC2E, formed in FP64) instead
  *                     of on equivalent densities (default 10; 17 = never).
+ *   "graph":          1 (default): an evaluation on a non-default stream is
+ *                     captured into a hipGraph on first use and replayed with
+ *                     one launch while tree, operators, precision, stream and
+ *                     buffers are unchanged (profiling runs eagerly); 0: eager.
  *   "m2l_fp64_sum_min_p": smallest order p at which an M2L that accumulates
  *                     in FP32 (FP32, BF16 and FP16 products) moves its sums
  *                     into FP64 after every operator step (default 10; 17 =

@@ -301,6 +301,11 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
     g_m2l_tile_cols = value;
     return KIFMM_OK;
   }
+  if (std::strcmp(key, "graph") == 0) {
+    if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: graph must be 0 or 1");
+    set_use_graphs(value != 0);
+    return KIFMM_OK;
+  }
   if (std::strcmp(key, "m2l_fp64_sum_min_p") == 0) {
     if (value < 2 || value > 17) return fail(KIFMM_EINVAL, "set_tuning: m2l_fp64_sum_min_p must be in [2, 17]");
     set_m2l_fp64_sum_min_p(value);

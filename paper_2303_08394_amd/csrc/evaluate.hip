@@ -101,7 +101,11 @@ struct DevForest {
   DevPlan m2l;
   std::vector<void*> allocs;
   std::map<std::pair<int, int>, DevWork*> work;  // (fp64, n_rhs)
+  // the last captured evaluation and what it was captured for
+  hipGraphExec_t graph = nullptr;
+  std::vector<const void*> graph_key;
   ~DevForest() {
+    if (graph) (void)hipGraphExecDestroy(graph);
     for (auto& w : work) delete w.second;
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -1404,6 +1408,11 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   }
 }
 
+// Evaluations on a non-default stream are captured once into a hipGraph and
+// replayed with one launch while the inputs of the capture stay the same.
+static bool g_use_graphs = true;
+void set_use_graphs(bool on) { g_use_graphs = on; }
+
 void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const void* const* charges,
                      void* const* potentials, int n_rhs, bool io_fp64, kifmm_precision prec,
                      void* stream) {
@@ -1428,13 +1437,54 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
   DevWork* W = work_for(F, fp64, n_rhs);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (fp64) {
-    if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
-    else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
-  } else {
-    if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
-    else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+  auto launch_all = [&]() {
+    if (fp64) {
+      if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+      else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+    } else {
+      if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+      else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+    }
+  };
+  if (!g_use_graphs || g_prof.on || s == nullptr) {
+    launch_all();
+    return;
   }
+  // everything the captured launches depend on
+  std::vector<const void*> key = {reinterpret_cast<const void*>(intptr_t(prec)),
+                                  reinterpret_cast<const void*>(intptr_t(n_rhs)),
+                                  reinterpret_cast<const void*>(intptr_t(io_fp64)), s, O, W,
+                                  reinterpret_cast<const void*>(intptr_t(g_far_fp64_min_p)),
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_check_min_p)),
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p))};
+  for (int k = 0; k < F.nprob; ++k) {
+    key.push_back(charges[k]);
+    key.push_back(potentials[k]);
+  }
+  if (!F.graph || F.graph_key != key) {
+    if (F.graph) {
+      HIPCHECK(hipGraphExecDestroy(F.graph));
+      F.graph = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_all();
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIPCHECK(hipStreamEndCapture(s, &g));
+    hipError_t ie = hipGraphInstantiate(&F.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      F.graph = nullptr;
+      raise(KIFMM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+    }
+    F.graph_key = key;
+  }
+  HIPCHECK(hipGraphLaunch(F.graph, s));
 }
 
 void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out) {

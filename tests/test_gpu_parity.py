@@ -173,3 +173,55 @@ def test_check_form_m2l(precision):
     e = rel(got, want)
     print(f"check-form {precision} rel L2 vs oracle = {e:.3e}")
     assert e < TOL32
+
+
+def test_graph_replays_match_eager():
+    """Captured evaluations replayed several times, with eager work and
+    synchronisation between the replays, equal the eager result bitwise."""
+    x, _ = I.uniform_cube(8000, seed=31)
+    rng = np.random.default_rng(31)
+    charges = [rng.uniform(-1, 1, 8000) for _ in range(4)]
+    tree = K.Tree(x, uniform_depth=3, **CUBE)
+    s = torch.cuda.Stream()
+    qbuf = torch.empty(8000, dtype=torch.float64, device=DEV)
+    obuf = torch.empty((1, 8000), dtype=torch.float64, device=DEV)
+    for prec in ("f16x3", "fp64"):
+        K.set_tuning("graph", 0)
+        eager = []
+        with torch.cuda.stream(s):
+            for c in charges:
+                qbuf.copy_(torch.as_tensor(c, device=DEV))
+                K.evaluate(tree, ops(5), qbuf, precision=prec, out=obuf)
+                s.synchronize()
+                eager.append(obuf.cpu().numpy().copy())
+        K.set_tuning("graph", 1)
+        try:
+            with torch.cuda.stream(s):
+                for rep in range(2):
+                    for c, want in zip(charges, eager):
+                        qbuf.copy_(torch.as_tensor(c, device=DEV))
+                        K.evaluate(tree, ops(5), qbuf, precision=prec, out=obuf)
+                        s.synchronize()
+                        junk = torch.randn(1000, device=DEV).sum()  # eager work between replays
+                        torch.cuda.synchronize()
+                        np.testing.assert_array_equal(obuf.cpu().numpy(), want)
+        finally:
+            K.set_tuning("graph", 1)
+
+
+def test_batch_graph_replays_match_eager():
+    probs = [I.clustered(n, seed=40 + n) for n in (3000, 5000, 2000)]
+    trees = [K.Tree(xx, ncrit=32, max_depth=10, **CUBE) for xx, _ in probs]
+    qs = [torch.as_tensor(q[0], dtype=torch.float64, device=DEV) for _, q in probs]
+    s = torch.cuda.Stream()
+    K.set_tuning("graph", 0)
+    with torch.cuda.stream(s):
+        eager = [o.cpu().numpy() for o in K.evaluate_batch(trees, ops(5), qs, precision="fp32")]
+    K.set_tuning("graph", 1)
+    outs = [torch.empty_like(q) for q in qs]
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            K.evaluate_batch(trees, ops(5), qs, precision="fp32", outs=outs)
+            s.synchronize()
+            for o, w in zip(outs, eager):
+                np.testing.assert_array_equal(o.cpu().numpy(), w)
