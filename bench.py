@@ -286,11 +286,16 @@ def main():
                 "achieved": flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s",
                 "issued_frac": issued * flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / peak}
-    else:
-        roof = {"kernel": "p2p_kernel (leaf)", "bound": "alu",
-                "achieved": leaf_pairs / (ms["leaf"] / launches["leaf"] * 1e-3) / 1e12,
+    elif dom == "near":
+        roof = {"kernel": "p2p_kernel (near field)", "bound": "alu",
+                "achieved": near_pairs * n_rhs / (ms["near"] / launches["near"] * 1e-3) / 1e12,
                 "peak": PEAK_PAIRS / 1e12, "unit": "Tpairs/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": None, "unit": None}
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof["peak"] else None
+    # the particle kernels, reported beside the dominant one
+    near_rate = near_pairs * n_rhs / (ms["near"] / max(launches["near"], 1) * 1e-3)
+    result["near_field"] = {"pairs_per_s": near_rate, "frac_of_valu_peak": near_rate / PEAK_PAIRS}
     roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
 
     line = {

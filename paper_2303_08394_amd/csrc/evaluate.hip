@@ -357,9 +357,10 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
 // profiling: HIP events around each phase on the evaluation stream
 // ------------------------------------------------------------------------
 
-enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L, PH_L2L, PH_DC2E, PH_LEAF, PH_SCATTER, PH_N };
-static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l",
-                                        "m2l", "l2l", "dc2e", "leaf", "scatter"};
+enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L, PH_L2L, PH_DC2E, PH_NEAR, PH_FAR,
+             PH_SCATTER, PH_N };
+static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l", "m2l",
+                                        "l2l", "dc2e", "near", "far", "scatter"};
 
 struct Profiler {
   bool on = false;
@@ -505,7 +506,9 @@ __global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
 // into LDS; targets are split into chunks of TCH lanes and the SL = 256/TCH
 // lane groups ("slices") stride over the staged sources, then reduce in FP64.
 
-enum { MODE_P2M = 0, MODE_P2L = 1, MODE_LEAF = 2 };
+// LEAF: near + far in one pass; NEAR: U lists only (writes the sums);
+// FAR: W lists and the own downward surface (adds to the sums).
+enum { MODE_P2M = 0, MODE_P2L = 1, MODE_LEAF = 2, MODE_NEAR = 3, MODE_FAR = 4 };
 enum { SEG_POINTS = 0, SEG_UP_EQUIV = 1, SEG_DN_EQUIV = 2 };
 
 template <class T>
@@ -580,7 +583,7 @@ __device__ inline void segment_info(const P2PArgs<T>& a, int wi, int B, int4 gB,
     id = sr.x;
     size = sr.y - sr.x;
     g = frame(a.box_geo[A], gB);
-  } else if (MODE == MODE_LEAF && si < nU + (a.l2_off[wi + 1] - a.l2_off[wi])) {
+  } else if (MODE != MODE_P2L && si < nU + (a.l2_off[wi + 1] - a.l2_off[wi])) {
     int A = a.l2_items[a.l2_off[wi] + (si - nU)];
     kind = SEG_UP_EQUIV;
     id = A;
@@ -740,11 +743,12 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
     nU = a.l1_off[wi + 1] - a.l1_off[wi];
     const int nW = a.l2_off[wi + 1] - a.l2_off[wi];
     nnear = nU;
-    nseg = nU + nW + (gB.w >= 2 ? 1 : 0);
+    nseg = MODE == MODE_NEAR ? nU : nU + nW + (gB.w >= 2 ? 1 : 0);
   }
+  constexpr bool LEAFLIKE = MODE == MODE_LEAF || MODE == MODE_NEAR || MODE == MODE_FAR;
   int nt, tbase = 0;
   double trad = 0.0;
-  if (MODE == MODE_LEAF) {
+  if (LEAFLIKE) {
     int2 tr = a.box_tgt[B];
     tbase = tr.x;
     nt = tr.y - tr.x;
@@ -761,7 +765,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       int t = t0 + c * TCH + ti;
       tx[c] = ty[c] = tz[c] = 0.0;
       if (t < nt) {
-        if (MODE == MODE_LEAF) {
+        if (LEAFLIKE) {
           double4 p = a.tgt64[tbase + t];
           tx[c] = p.x;
           ty[c] = p.y;
@@ -777,8 +781,9 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       for (int r = 0; r < RC; ++r) acc[c][r] = 0.0;
     }
     const int nchunks = (min(nt - t0, TCH * kNch) + TCH - 1) / TCH;
-    p2p_phase<T, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks, acc);
-    if (nseg > nnear)
+    if (MODE != MODE_FAR)
+      p2p_phase<T, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks, acc);
+    if (MODE != MODE_NEAR && nseg > nnear)
       p2p_phase<TF, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz, nchunks, acc);
 
     // reduce the slices of each chunk and write
@@ -799,8 +804,10 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
               for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * TCH + ti) * RC + r];
               const int rr = rhs0 + r;
               if (rr < a.n_rhs) {
-                if (MODE == MODE_LEAF) {
+                if (MODE == MODE_LEAF || MODE == MODE_NEAR) {
                   a.pot[int64_t(rr) * a.ntgt + tbase + t] = sum * (kInv4Pi / rB);
+                } else if (MODE == MODE_FAR) {
+                  a.pot[int64_t(rr) * a.ntgt + tbase + t] += sum * (kInv4Pi / rB);
                 } else {
                   T* o = a.out_col + (int64_t(B) * a.n_rhs + rr) * a.ld + t;
                   if (MODE == MODE_P2M) *o = T(sum * kInv4Pi);
@@ -964,6 +971,10 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   }
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  // waves form a 2 x 2 grid: wr picks half of the row blocks, wc half of the
+  // column blocks, so each operator fragment is read by two waves, not four
+  constexpr int RBW = kRB / 2, CBW = 2 * CB;
+  const int wr = wave >> 1, wc = wave & 1;
   const int tile = blockIdx.x;
   const int row0 = blockIdx.y * kROWS;
   const int nrb = min(kRB, (a.ld - row0) / 16);
@@ -973,22 +984,22 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   const int kcs = ld / KC;  // chunks per step
   const int nchunks = (se - sb) * kcs;
 
-  ACC acc[kRB][CB];
+  ACC acc[RBW][CBW];
 #pragma unroll
-  for (int i = 0; i < kRB; ++i)
+  for (int i = 0; i < RBW; ++i)
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
+    for (int c = 0; c < CBW; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][c][v] = 0;
   // TAG 2: after every operator step the FP32 sums are moved into FP64
   // registers, so FP32 rounding spans one step (one n x n product) only
   constexpr bool FLUSH = TAG == 2 && MODE != GM_F64;
-  f64x4 acc64[FLUSH ? kRB : 1][FLUSH ? CB : 1];
+  f64x4 acc64[FLUSH ? RBW : 1][FLUSH ? CBW : 1];
   if constexpr (FLUSH) {
 #pragma unroll
-    for (int i = 0; i < kRB; ++i)
+    for (int i = 0; i < RBW; ++i)
 #pragma unroll
-      for (int c = 0; c < CB; ++c)
+      for (int c = 0; c < CBW; ++c)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc64[i][c][v] = 0.0;
   }
@@ -1083,27 +1094,27 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     if constexpr (!BF) {
       // all fragments of the chunk first, then k-outer / row-block-inner so
       // that consecutive MFMAs accumulate into different registers
-      TA bv[CB][KL], av[kRB][KL];
+      TA bv[CBW][KL], av[RBW][KL];
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const TA* p = Bs + (wave * 16 * CB + c * 16 + r16) * SA + g * KL;
+      for (int c = 0; c < CBW; ++c) {
+        const TA* p = Bs + (wc * 16 * CBW + c * 16 + r16) * SA + g * KL;
 #pragma unroll
         for (int e = 0; e < KL; ++e) bv[c][e] = p[e];
       }
       // rows past ld are staged as zeros, so every row block is computed
       // unconditionally; only the epilogue skips them
 #pragma unroll
-      for (int i = 0; i < kRB; ++i) {
-        const TA* p = As + (i * 16 + r16) * SA + g * KL;
+      for (int i = 0; i < RBW; ++i) {
+        const TA* p = As + ((wr * RBW + i) * 16 + r16) * SA + g * KL;
 #pragma unroll
         for (int e = 0; e < KL; ++e) av[i][e] = p[e];
       }
 #pragma unroll
       for (int e = 0; e < KL; ++e)
 #pragma unroll
-        for (int i = 0; i < kRB; ++i)
+        for (int i = 0; i < RBW; ++i)
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
+            for (int c = 0; c < CBW; ++c) {
               if constexpr (MODE == GM_F32)
                 acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][e], bv[c][e], acc[i][c], 0, 0, 0);
               else
@@ -1115,20 +1126,21 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
         if constexpr (MODE == GM_H3) return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
         else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
       };
-      vec8 bh[CB], bm[CB], bl[CB];
+      vec8 bh[CBW], bm[CBW], bl[CBW];
 #pragma unroll
-      for (int c = 0; c < CB; ++c) {
-        const int col = wave * 16 * CB + c * 16 + r16;
+      for (int c = 0; c < CBW; ++c) {
+        const int col = wc * 16 * CBW + c * 16 + r16;
         bh[c] = *reinterpret_cast<const vec8*>(Bs + col * SA + g * 8);
         bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * TC * SA + col * SA + g * 8);
         if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + TC * SA + col * SA + g * 8);
       }
 #pragma unroll
-      for (int i = 0; i < kRB; ++i) {
-        const vec8 ah = *reinterpret_cast<const vec8*>(As + (i * 16 + r16) * SA + g * 8);
-        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * SA + (i * 16 + r16) * SA + g * 8);
+      for (int i = 0; i < RBW; ++i) {
+        const int arow = (wr * RBW + i) * 16 + r16;
+        const vec8 ah = *reinterpret_cast<const vec8*>(As + arow * SA + g * 8);
+        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * SA + arow * SA + g * 8);
 #pragma unroll
-        for (int c = 0; c < CB; ++c) {
+        for (int c = 0; c < CBW; ++c) {
           acc[i][c] = mma(ah, bh[c], acc[i][c]);
           acc[i][c] = mma(al, bh[c], acc[i][c]);
           if constexpr (NB == 3) {
@@ -1152,9 +1164,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
       if constexpr (FLUSH) {
         if ((ch + 1) % kcs == 0) {
 #pragma unroll
-          for (int i = 0; i < kRB; ++i)
+          for (int i = 0; i < RBW; ++i)
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
+            for (int c = 0; c < CBW; ++c)
 #pragma unroll
               for (int v = 0; v < 4; ++v) {
                 acc64[i][c][v] += double(acc[i][c][v]);
@@ -1168,19 +1180,19 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   }
 
 #pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    const int s = wave * 16 * CB + c * 16 + r16;
+  for (int c = 0; c < CBW; ++c) {
+    const int s = wc * 16 * CBW + c * 16 + r16;
     if (s < ncols) {
       const int b = s / a.n_rhs, r = s % a.n_rhs;
       const int box = a.tile_cols[int64_t(tile) * a.TB + b];
       if (box >= 0) {
         TO* o = static_cast<TO*>(a.out) + (int64_t(box) * a.n_rhs + r) * ld;
 #pragma unroll
-        for (int i = 0; i < kRB; ++i) {
-          if (i < nrb) {
+        for (int i = 0; i < RBW; ++i) {
+          if (wr * RBW + i < nrb) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int row = row0 + i * 16 + G::row(lane, v);
+              const int row = row0 + (wr * RBW + i) * 16 + G::row(lane, v);
               // summed in the wider of the accumulator and output types
               using TAcc = typename std::conditional<(sizeof(TO) > sizeof(acc[0][0][0])), TO,
                                                      decltype(acc[0][0][0] + 0)>::type;
@@ -1248,12 +1260,30 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64,
   }
 }
 
+// Per-device auxiliary stream and fork/join events of the pipeline (default
+// priority, non-blocking; created once and kept for the process).
+struct Aux {
+  hipStream_t stream = nullptr;
+  hipEvent_t forked = nullptr, joined = nullptr;
+};
+static Aux& aux_for(int dev) {
+  static std::map<int, Aux> m;
+  Aux& x = m[dev];
+  if (!x.stream) {
+    HIPCHECK(hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&x.forked, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&x.joined, hipEventDisableTiming));
+  }
+  return x;
+}
+
 template <class T, class TIO>
 static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* charges,
                      void* const* potentials, int n_rhs, kifmm_precision prec, bool check_form,
                      hipStream_t s) {
   constexpr int GF = sizeof(T) == 8 ? GM_F64 : GM_F32;
   const int ld = F.ld;
+  Aux& aux = aux_for(current_device());
   const int64_t nn = int64_t(ld) * ld;
   T* qs = static_cast<T*>(W.qs);
   T* up_chk = static_cast<T*>(W.up_chk);
@@ -1300,6 +1330,21 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.dn_eq = dn_eq;
   base.pot = W.pot;
   base.ntgt = F.ntgt;
+  {
+    // fork: the near field needs only the gathered charges; it runs on the
+    // auxiliary stream while the multipole passes run on s
+    HIPCHECK(hipEventRecord(aux.forked, s));
+    HIPCHECK(hipStreamWaitEvent(aux.stream, aux.forked, 0));
+    PhaseScope ps(PH_NEAR, aux.stream);
+    P2PArgs<T> a = base;
+    a.work = F.leaf_boxes;
+    a.l1_off = F.u_off;
+    a.l1_items = F.u_items;
+    a.l2_off = F.w_off;
+    a.l2_items = F.w_items;
+    run_p2p_rc<T, MODE_NEAR, 32>(a, F.n_leaf, n_rhs, false, aux.stream, ps);
+  }
+  HIPCHECK(hipEventRecord(aux.joined, aux.stream));
   {
     PhaseScope ps(PH_P2M, s);
     P2PArgs<T> a = base;
@@ -1383,7 +1428,9 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     }
   }
   {
-    PhaseScope ps(PH_LEAF, s);
+    // join the near field, then add the far field (L2P + M2P)
+    HIPCHECK(hipStreamWaitEvent(s, aux.joined, 0));
+    PhaseScope ps(PH_FAR, s);
     P2PArgs<T> a = base;
     a.work = F.leaf_boxes;
     a.l1_off = F.u_off;
@@ -1391,7 +1438,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.l2_off = F.w_off;
     a.l2_items = F.w_items;
     const bool far64 = sizeof(T) == 4 && O.p >= g_far_fp64_min_p;
-    run_p2p_rc<T, MODE_LEAF, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
+    run_p2p_rc<T, MODE_FAR, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
   }
   {
     PhaseScope ps(PH_SCATTER, s);
