@@ -54,11 +54,12 @@ struct DevOps {
   double *uc2e = nullptr, *dc2e = nullptr;               // [ld][ld]
   float *m2m32 = nullptr, *l2l32 = nullptr, *m2l32 = nullptr;  // [k][ld][ld]
   double *m2m64 = nullptr, *l2l64 = nullptr, *m2l64 = nullptr;
-  uint16_t *m2l_bh = nullptr, *m2l_bl = nullptr;         // BF16 high/low parts of M2L
-  uint16_t *m2l_hh = nullptr, *m2l_hl = nullptr;         // FP16 parts of 2^10 M2L
+  // split tables, [316][ld][2][ld]: each operator row as high part, low part
+  uint16_t* m2l_b = nullptr;    // BF16 parts of M2L
+  uint16_t* m2l_h = nullptr;    // FP16 parts of 2^10 M2L
   // check-potential form (M2L folded with UC2E): FP32 and FP16 parts
   float* m2lc32 = nullptr;
-  uint16_t *m2lc_hh = nullptr, *m2lc_hl = nullptr;
+  uint16_t* m2lc_h = nullptr;
   double4* surf = nullptr;                               // [n] unit-cube surface
   std::vector<void*> allocs;
   ~DevOps() {
@@ -142,7 +143,8 @@ static D* dev_upload(std::vector<void*>& allocs, const std::vector<S>& v) {
   return p;
 }
 
-static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P) {
+// Absent sources (-1) become the zero box, so the GEMM never branches on them.
+static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P, int32_t zero_box) {
   DevPlan d;
   d.ntile = P.ntile;
   d.TB = P.TB;
@@ -152,7 +154,10 @@ static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P) {
   d.tile_cols = dev_upload<int32_t>(allocs, P.tile_cols);
   d.step_beg = dev_upload<int32_t>(allocs, P.step_beg);
   d.step_op = dev_upload<int32_t>(allocs, P.step_op);
-  d.step_src = dev_upload<int32_t>(allocs, P.step_src);
+  std::vector<int32_t> src(P.step_src);
+  for (auto& v : src)
+    if (v < 0) v = zero_box;
+  d.step_src = dev_upload<int32_t>(allocs, src);
   return d;
 }
 
@@ -197,11 +202,11 @@ static DevForest* upload_forest(const HostForest& F, int n) {
     D->n_x = int32_t(F.x_boxes.size());
     D->x_off = dev_upload<int32_t>(A, F.x_off);
     D->x_items = dev_upload<int32_t>(A, F.x_items);
-    for (auto& p : F.m2m) D->m2m.push_back(upload_plan(A, p));
-    for (auto& p : F.uc2e) D->uc2e.push_back(upload_plan(A, p));
-    for (auto& p : F.l2l) D->l2l.push_back(upload_plan(A, p));
-    for (auto& p : F.dc2e) D->dc2e.push_back(upload_plan(A, p));
-    D->m2l = upload_plan(A, F.m2l);
+    for (auto& p : F.m2m) D->m2m.push_back(upload_plan(A, p, F.nbox));
+    for (auto& p : F.uc2e) D->uc2e.push_back(upload_plan(A, p, F.nbox));
+    for (auto& p : F.l2l) D->l2l.push_back(upload_plan(A, p, F.nbox));
+    for (auto& p : F.dc2e) D->dc2e.push_back(upload_plan(A, p, F.nbox));
+    D->m2l = upload_plan(A, F.m2l, F.nbox);
   } catch (...) {
     delete D;
     throw;
@@ -256,17 +261,27 @@ void set_m2l_check_min_p(int p) { g_m2l_check_min_p = p; }
 static int g_m2l_fp64_sum_min_p = 10;
 void set_m2l_fp64_sum_min_p(int p) { g_m2l_fp64_sum_min_p = p; }
 
-static void upload_split16(DevOps* O, const std::vector<double>& pad, uint16_t** hi_out,
-                           uint16_t** lo_out) {
-  std::vector<uint16_t> hi(pad.size()), lo(pad.size());
+// Interleaves the high and low parts of every operator row: [k][ld][2][ld].
+template <class Split>
+static uint16_t* upload_split(DevOps* O, const std::vector<double>& pad, Split split) {
+  const size_t ld = size_t(O->ld), rows = pad.size() / ld;
+  std::vector<uint16_t> out(2 * pad.size());
+  for (size_t r = 0; r < rows; ++r)
+    for (size_t j = 0; j < ld; ++j) {
+      uint16_t hi, lo;
+      split(pad[r * ld + j], hi, lo);
+      out[(2 * r) * ld + j] = hi;
+      out[(2 * r + 1) * ld + j] = lo;
+    }
+  return dev_upload<uint16_t>(O->allocs, out);
+}
+static uint16_t* upload_split16(DevOps* O, const std::vector<double>& pad) {
   const double sc = std::ldexp(1.0, kF16OpExp);
-  for (size_t i = 0; i < pad.size(); ++i) {
-    const double v = pad[i] * sc;
-    hi[i] = f16_bits(v);
-    lo[i] = f16_bits(v - f16_value(hi[i]));
-  }
-  *hi_out = dev_upload<uint16_t>(O->allocs, hi);
-  *lo_out = dev_upload<uint16_t>(O->allocs, lo);
+  return upload_split(O, pad, [&](double x, uint16_t& hi, uint16_t& lo) {
+    const double v = x * sc;
+    hi = f16_bits(v);
+    lo = f16_bits(v - f16_value(hi));
+  });
 }
 
 // Which tables an evaluation needs: bulk type (FP32 or FP64 M2M/L2L), and the
@@ -300,9 +315,9 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
   if (need.m2l64 && !O->m2l64)
     O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
   if (need.check_form) {
-    if ((need.f16 && !O->m2lc_hh) || (need.m2l32 && !O->m2lc32)) {
+    if ((need.f16 && !O->m2lc_h) || (need.m2l32 && !O->m2lc32)) {
       std::vector<double> pad = pad_table<double>(m2l_check_form(H), kNumM2L, H.n, O->ld);
-      if (need.f16 && !O->m2lc_hh) upload_split16(O, pad, &O->m2lc_hh, &O->m2lc_hl);
+      if (need.f16 && !O->m2lc_h) O->m2lc_h = upload_split16(O, pad);
       if (need.m2l32 && !O->m2lc32) {
         std::vector<float> f(pad.begin(), pad.end());
         O->m2lc32 = dev_upload<float>(O->allocs, f);
@@ -311,21 +326,14 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
   } else {
     if (need.m2l32 && !O->m2l32)
       O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L, H.n, O->ld));
-    if (need.f16 && !O->m2l_hh) {
-      std::vector<double> pad = pad_table<double>(H.m2l, kNumM2L, H.n, O->ld);
-      upload_split16(O, pad, &O->m2l_hh, &O->m2l_hl);
-    }
+    if (need.f16 && !O->m2l_h) O->m2l_h = upload_split16(O, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
   }
-  if (need.bf16 && !O->m2l_bh) {
-    std::vector<double> pad = pad_table<double>(H.m2l, kNumM2L, H.n, O->ld);
-    std::vector<uint16_t> hi(pad.size()), lo(pad.size());
-    for (size_t i = 0; i < pad.size(); ++i) {
-      hi[i] = bf16_bits(float(pad[i]));
-      lo[i] = bf16_bits(float(pad[i] - bf16_value(hi[i])));
-    }
-    O->m2l_bh = dev_upload<uint16_t>(O->allocs, hi);
-    O->m2l_bl = dev_upload<uint16_t>(O->allocs, lo);
-  }
+  if (need.bf16 && !O->m2l_b)
+    O->m2l_b = upload_split(O, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld),
+                            [](double x, uint16_t& hi, uint16_t& lo) {
+                              hi = bf16_bits(float(x));
+                              lo = bf16_bits(float(x - bf16_value(hi)));
+                            });
   return O;
 }
 
@@ -336,7 +344,8 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
   W->n_rhs = n_rhs;
   W->fp64 = fp64;
   size_t es = fp64 ? 8 : 4;
-  size_t cols = size_t(F.nbox) * n_rhs * F.ld;
+  // one extra box: the zero columns that empty GEMM slots read
+  size_t cols = size_t(F.nbox + 1) * n_rhs * F.ld;
   W->col_bytes = cols * es;
   auto alloc_bytes = [&](size_t bytes) {
     void* p = dev_alloc<unsigned char>(W->allocs, bytes);
@@ -842,6 +851,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));  // 16-byte staging unit
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
@@ -853,38 +863,37 @@ template <int MODE> struct GT;
 template <> struct GT<GM_F32> {
   using TA = float;       // LDS element of both operands
   using acc = f32x4;
-  static constexpr int KC = 32, NB = 1, SA = KC + 4;
+  static constexpr int KC = 32, NB = 1;
   // output layout of 16x16 products: lane l, register v -> D[row(l,v)][l%16]
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct GT<GM_F64> {
   using TA = double;
   using acc = f64x4;
-  static constexpr int KC = 16, NB = 1, SA = KC + 2;
+  static constexpr int KC = 16, NB = 1;
   __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
 };
 template <> struct GT<GM_BF3> {
   using TA = __bf16;
   using acc = f32x4;
-  static constexpr int KC = 32, NB = 2, SA = KC + 8;
+  static constexpr int KC = 32, NB = 2;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct GT<GM_BF5> {
   using TA = __bf16;
   using acc = f32x4;
-  static constexpr int KC = 32, NB = 3, SA = KC + 8;
+  static constexpr int KC = 32, NB = 3;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 template <> struct GT<GM_H3> {
   using TA = _Float16;
   using acc = f32x4;
-  static constexpr int KC = 32, NB = 2, SA = KC + 8;
+  static constexpr int KC = 32, NB = 2;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
 struct GemmArgs {
-  const void* ops;      // FP32/FP64: [nop][ld][ld]; BF: high parts [nop][ld][ld]
-  const void* ops_lo;   // BF: low parts
+  const void* ops;      // [nop][ld rows][NA parts][ld]; NA = 2 for split modes (high, low)
   int64_t op_stride;    // elements between operators (0: one operator)
   int ld, n_rhs, accumulate, TB;
   const void* in;       // columns [ncol][ld] of TI
@@ -894,6 +903,7 @@ struct GemmArgs {
   const int32_t* step_op;
   const int32_t* step_src;
   const unsigned* absmax;  // FP16 split: bits of max |input| (non-negative float)
+  int zero_box;            // box index of the all-zero columns (the forest's nbox)
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
@@ -902,10 +912,10 @@ template <int MODE, class TI, class TO, int CB>
 struct GemmCfg {
   using G = GT<MODE>;
   using TA = typename G::TA;
-  static constexpr int KC = G::KC, SA = G::SA, NB = G::NB, TC = 64 * CB;
+  static constexpr int KC = G::KC, NB = G::NB, TC = 64 * CB;
   static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3) ? 2 : 1;  // operator tables
-  // per buffer: NA operator tiles [ROWS][SA] and NB column tiles [TC][SA] of TA
-  static constexpr int A_ELEMS = NA * kROWS * SA, B_ELEMS = NB * TC * SA;
+  // per buffer: NA operator tiles [ROWS][KC] and NB column tiles [TC][KC] of TA
+  static constexpr int A_ELEMS = NA * kROWS * KC, B_ELEMS = NB * TC * KC;
   static constexpr int BUF_BYTES = (A_ELEMS + B_ELEMS) * int(sizeof(TA));
   // 16-byte global units per chunk
   static constexpr int A_UNITS_ROW = KC * int(sizeof(TA)) / 16;         // per table row
@@ -914,6 +924,14 @@ struct GemmCfg {
   static constexpr int B_UNITS_COL = KC * int(sizeof(TI)) / 16;
   static constexpr int B_UNITS = TC * B_UNITS_COL;
   static constexpr int B_PER_T = (B_UNITS + 255) / 256;
+  // LDS rows are KC elements with no padding; the 16-byte chunks of a row are
+  // XOR-swizzled so that a chunk column of consecutive rows (a fragment read,
+  // or a staging store) falls into distinct banks.
+  static constexpr int EPC = 16 / int(sizeof(TA));            // elements per chunk
+  static constexpr int CPR = KC * int(sizeof(TA)) / 16;       // chunks per row
+  static constexpr int RPW = 128 / (KC * int(sizeof(TA)));    // rows per 128-byte bank window
+  __device__ static int swz(int row, int chunk) { return chunk ^ ((row / RPW) & (CPR - 1)); }
+  __device__ static int off(int row, int chunk) { return row * KC + swz(row, chunk) * EPC; }
 };
 
 // Splits 4 (or 2) inputs x*scale into nb low-precision parts, written as one
@@ -954,7 +972,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   using G = GT<MODE>;
   using TA = typename Cfg::TA;
   using ACC = typename G::acc;
-  constexpr int KC = Cfg::KC, SA = Cfg::SA, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
+  constexpr int KC = Cfg::KC, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
   constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
   __shared__ __align__(16) unsigned char smem[2 * Cfg::BUF_BYTES];
   // FP16 split: exact power-of-two scaling of the densities into range
@@ -1004,110 +1022,125 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
         for (int v = 0; v < 4; ++v) acc64[i][c][v] = 0.0;
   }
 
-  uint4 ra[Cfg::A_PER_T], rb[Cfg::B_PER_T];
+  // registers of the chunk in flight from global memory
+  u32x4 ra[Cfg::A_PER_T], rb[Cfg::B_PER_T];
   int64_t bcol[Cfg::B_PER_T];
   int cur_step = -1;
 
-  auto load_regs = [&](int ch) {
+  // Per-thread staging addresses, fixed for the whole tile: operator units
+  // (row, part, split part) and the LDS slots they land in.  Operator rows
+  // past ld are clamped to a valid row: they only feed output rows that the
+  // epilogue discards.
+  static_assert(Cfg::A_UNITS % 256 == 0 && Cfg::B_UNITS % 256 == 0, "staging units per thread");
+  int a_goff[Cfg::A_PER_T], a_loff[Cfg::A_PER_T];
+#pragma unroll
+  for (int j = 0; j < Cfg::A_PER_T; ++j) {
+    const int u = tid + j * 256;
+    const int rl = u / (NA * Cfg::CPR), t = (u / Cfg::CPR) % NA, part = u % Cfg::CPR;
+    const int rg = min(row0 + rl, ld - 1);
+    a_goff[j] = (rg * NA + t) * ld + part * Cfg::EPC;
+    a_loff[j] = t * kROWS * KC + Cfg::off(rl, part);
+  }
+  int b_goff[Cfg::B_PER_T];
+  const int zero_col = a.zero_box * a.n_rhs;  // an all-zero column for empty slots
+
+  auto load_regs = [&](int ch) __attribute__((always_inline)) {
     const int st = sb + ch / kcs;
     const int k0 = (ch % kcs) * KC;
-    const int64_t opoff = int64_t(a.step_op[st]) * a.op_stride;
+    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(a.step_op[st]) * a.op_stride + k0;
 #pragma unroll
-    for (int j = 0; j < Cfg::A_PER_T; ++j) {
-      const int u = tid + j * 256;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (u < Cfg::A_UNITS) {
-        const int t = u / (kROWS * Cfg::A_UNITS_ROW);
-        const int uu = u % (kROWS * Cfg::A_UNITS_ROW);
-        const int row = row0 + uu / Cfg::A_UNITS_ROW, part = uu % Cfg::A_UNITS_ROW;
-        if (row < ld) {
-          const TA* base = static_cast<const TA*>(t == 0 ? a.ops : a.ops_lo);
-          v = *reinterpret_cast<const uint4*>(base + opoff + int64_t(row) * ld + k0 + part * (16 / int(sizeof(TA))));
-        }
-      }
-      ra[j] = v;
-    }
+    for (int j = 0; j < Cfg::A_PER_T; ++j) ra[j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
     if (st != cur_step) {
       // source columns of this thread's B units for the new step
       cur_step = st;
 #pragma unroll
       for (int j = 0; j < Cfg::B_PER_T; ++j) {
         const int u = tid + j * 256;
-        const int s = u / Cfg::B_UNITS_COL;
-        int64_t col = -1;
-        if (u < Cfg::B_UNITS && s < ncols) {
-          const int src = a.step_src[int64_t(st) * a.TB + s / a.n_rhs];
-          if (src >= 0) col = int64_t(src) * a.n_rhs + s % a.n_rhs;
-        }
-        bcol[j] = col;
+        const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
+        int col = zero_col;
+        if (s < ncols) col = a.step_src[int64_t(st) * a.TB + s / a.n_rhs] * a.n_rhs + s % a.n_rhs;
+        b_goff[j] = col * ld + part * (16 / int(sizeof(TI)));
       }
     }
+    const TI* inb = static_cast<const TI*>(a.in) + k0;
 #pragma unroll
-    for (int j = 0; j < Cfg::B_PER_T; ++j) {
-      const int part = (tid + j * 256) % Cfg::B_UNITS_COL;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (bcol[j] >= 0)
-        v = *reinterpret_cast<const uint4*>(static_cast<const TI*>(a.in) + bcol[j] * ld + k0 +
-                                            part * (16 / int(sizeof(TI))));
-      rb[j] = v;
-    }
+    for (int j = 0; j < Cfg::B_PER_T; ++j) rb[j] = *reinterpret_cast<const u32x4*>(inb + b_goff[j]);
   };
 
-  auto store_lds = [&](int buf) {
+  auto store_lds = [&](int buf) __attribute__((always_inline)) {
     TA* As = reinterpret_cast<TA*>(smem + buf * Cfg::BUF_BYTES);
     TA* Bs = As + Cfg::A_ELEMS;
 #pragma unroll
-    for (int j = 0; j < Cfg::A_PER_T; ++j) {
-      const int u = tid + j * 256;
-      if (u < Cfg::A_UNITS) {
-        const int t = u / (kROWS * Cfg::A_UNITS_ROW);
-        const int uu = u % (kROWS * Cfg::A_UNITS_ROW);
-        const int i = uu / Cfg::A_UNITS_ROW, part = uu % Cfg::A_UNITS_ROW;
-        *reinterpret_cast<uint4*>(As + t * kROWS * SA + i * SA + part * (16 / int(sizeof(TA)))) = ra[j];
-      }
-    }
+    for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[j];
     constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
       const int u = tid + j * 256;
-      if (u < Cfg::B_UNITS) {
+      {
         const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
         const TI* vals = reinterpret_cast<const TI*>(&rb[j]);
-        if constexpr (BF) {
-          TA* h = Bs + s * SA + part * EPU;
-          TA* m = h + TC * SA;
-          TA* l = h + (NB - 1) * TC * SA;
-          split_store<TA, NB, TI, EPU>(h, m, l, vals, in_scale);
-        } else {
-          TA* d = Bs + s * SA + part * EPU;
+        // input unit `part` holds k = part*EPU .. part*EPU + EPU - 1
+        constexpr int EPC = Cfg::EPC;
+        if constexpr (EPU >= EPC) {
+          // one or more whole LDS chunks
 #pragma unroll
-          for (int e = 0; e < EPU; ++e) d[e] = TA(vals[e]);
+          for (int q = 0; q < EPU / EPC; ++q) {
+            const int chunk = part * (EPU / EPC) + q;
+            if constexpr (BF) {
+              TA* h = Bs + Cfg::off(s, chunk);
+              split_store<TA, NB, TI, EPC>(h, h + TC * KC, h + (NB - 1) * TC * KC, vals + q * EPC, in_scale);
+            } else {
+              TA* d = Bs + Cfg::off(s, chunk);
+#pragma unroll
+              for (int x = 0; x < EPC; ++x) d[x] = TA(vals[q * EPC + x]);
+            }
+          }
+        } else {
+          // part of one LDS chunk
+          const int k0 = part * EPU;
+          TA* d = Bs + Cfg::off(s, k0 / EPC) + k0 % EPC;
+          if constexpr (BF) {
+            split_store<TA, NB, TI, EPU>(d, d + TC * KC, d + (NB - 1) * TC * KC, vals, in_scale);
+          } else {
+#pragma unroll
+            for (int x = 0; x < EPU; ++x) d[x] = TA(vals[x]);
+          }
         }
       }
     }
   };
 
-  auto compute = [&](int buf) {
+  auto compute = [&](int buf) __attribute__((always_inline)) {
     const TA* As = reinterpret_cast<const TA*>(smem + buf * Cfg::BUF_BYTES);
     const TA* Bs = As + Cfg::A_ELEMS;
     constexpr int KL = KC / 4;  // k values per lane per chunk
     if constexpr (!BF) {
       // all fragments of the chunk first, then k-outer / row-block-inner so
-      // that consecutive MFMAs accumulate into different registers
+      // that consecutive MFMAs accumulate into different registers.  Lane
+      // group g carries k = g*KL .. g*KL + KL - 1: chunks g*KL/EPC onwards.
+      constexpr int EPC = Cfg::EPC, NCH = KL / EPC;
       TA bv[CBW][KL], av[RBW][KL];
 #pragma unroll
       for (int c = 0; c < CBW; ++c) {
-        const TA* p = Bs + (wc * 16 * CBW + c * 16 + r16) * SA + g * KL;
+        const int col = wc * 16 * CBW + c * 16 + r16;
 #pragma unroll
-        for (int e = 0; e < KL; ++e) bv[c][e] = p[e];
+        for (int q = 0; q < NCH; ++q) {
+          const TA* p = Bs + Cfg::off(col, g * NCH + q);
+#pragma unroll
+          for (int x = 0; x < EPC; ++x) bv[c][q * EPC + x] = p[x];
+        }
       }
       // rows past ld are staged as zeros, so every row block is computed
       // unconditionally; only the epilogue skips them
 #pragma unroll
       for (int i = 0; i < RBW; ++i) {
-        const TA* p = As + ((wr * RBW + i) * 16 + r16) * SA + g * KL;
+        const int arow = (wr * RBW + i) * 16 + r16;
 #pragma unroll
-        for (int e = 0; e < KL; ++e) av[i][e] = p[e];
+        for (int q = 0; q < NCH; ++q) {
+          const TA* p = As + Cfg::off(arow, g * NCH + q);
+#pragma unroll
+          for (int x = 0; x < EPC; ++x) av[i][q * EPC + x] = p[x];
+        }
       }
 #pragma unroll
       for (int e = 0; e < KL; ++e)
@@ -1130,15 +1163,16 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 #pragma unroll
       for (int c = 0; c < CBW; ++c) {
         const int col = wc * 16 * CBW + c * 16 + r16;
-        bh[c] = *reinterpret_cast<const vec8*>(Bs + col * SA + g * 8);
-        bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * TC * SA + col * SA + g * 8);
-        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + TC * SA + col * SA + g * 8);
+        const int o = Cfg::off(col, g);
+        bh[c] = *reinterpret_cast<const vec8*>(Bs + o);
+        bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * TC * KC + o);
+        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + TC * KC + o);
       }
 #pragma unroll
       for (int i = 0; i < RBW; ++i) {
-        const int arow = (wr * RBW + i) * 16 + r16;
-        const vec8 ah = *reinterpret_cast<const vec8*>(As + arow * SA + g * 8);
-        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * SA + arow * SA + g * 8);
+        const int o = Cfg::off((wr * RBW + i) * 16 + r16, g);
+        const vec8 ah = *reinterpret_cast<const vec8*>(As + o);
+        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * KC + o);
 #pragma unroll
         for (int c = 0; c < CBW; ++c) {
           acc[i][c] = mma(ah, bh[c], acc[i][c]);
@@ -1153,6 +1187,22 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     }
   };
 
+  auto flush = [&](int ch) __attribute__((always_inline)) {
+    if constexpr (FLUSH) {
+      if ((ch + 1) % kcs == 0) {
+#pragma unroll
+        for (int i = 0; i < RBW; ++i)
+#pragma unroll
+          for (int c = 0; c < CBW; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              acc64[i][c][v] += double(acc[i][c][v]);
+              acc[i][c][v] = 0;
+            }
+      }
+    }
+  };
+
   if (nchunks > 0) {
     load_regs(0);
     store_lds(0);
@@ -1161,19 +1211,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
       const int buf = ch & 1;
       if (ch + 1 < nchunks) load_regs(ch + 1);
       compute(buf);
-      if constexpr (FLUSH) {
-        if ((ch + 1) % kcs == 0) {
-#pragma unroll
-          for (int i = 0; i < RBW; ++i)
-#pragma unroll
-            for (int c = 0; c < CBW; ++c)
-#pragma unroll
-              for (int v = 0; v < 4; ++v) {
-                acc64[i][c][v] += double(acc[i][c][v]);
-                acc[i][c][v] = 0;
-              }
-        }
-      }
+      flush(ch);
       if (ch + 1 < nchunks) store_lds(buf ^ 1);
       __syncthreads();
     }
@@ -1213,16 +1251,18 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 // pipeline
 // ------------------------------------------------------------------------
 
+// zero_box: the forest's box count; the columns of that box in every buffer
+// are allocated, zero, and never written.
 template <int MODE, class TI, class TO, int TAG = 0>
-static void run_gemm(const DevPlan& P, const void* ops, const void* ops_lo, int64_t op_stride,
-                     int ld, int n_rhs, const TI* in, TO* out, bool accumulate, hipStream_t s,
+static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int ld, int zero_box,
+                     int n_rhs, const TI* in, TO* out, bool accumulate, hipStream_t s,
                      PhaseScope& ps, const unsigned* absmax = nullptr) {
   if (P.ntile == 0) return;
   const int ncols = P.TB * n_rhs;
   if (ncols > 128) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
-  GemmArgs g{ops, ops_lo, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
-             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax};
+  GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
+             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
   if (ncols > 64)
     hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG>), grid, dim3(256), 0, s, g);
@@ -1355,11 +1395,11 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   for (int l = F.depth; l >= 2; --l) {
     {
       PhaseScope ps(PH_M2M, s);
-      run_gemm<GF, T, T>(F.m2m[l], m2m, nullptr, nn, ld, n_rhs, up_eq, up_chk, false, s, ps);
+      run_gemm<GF, T, T>(F.m2m[l], m2m, nn, ld, F.nbox, n_rhs, up_eq, up_chk, false, s, ps);
     }
     {
       PhaseScope ps(PH_UC2E, s);
-      run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, nullptr, 0, ld, n_rhs, up_chk, up_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, 0, ld, F.nbox, n_rhs, up_chk, up_eq, false, s, ps);
     }
   }
   {
@@ -1392,39 +1432,38 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       ps.launches += 2;
     };
     const bool fp64_sum = O.p >= g_m2l_fp64_sum_min_p;
-    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const void* opb, const T* in,
-                            const unsigned* amax) {
+    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const T* in, const unsigned* amax) {
       constexpr int MODE = decltype(mode_tag)::value;
+      constexpr int64_t parts = (MODE == GM_F32 || MODE == GM_F64) ? 1 : 2;
       if (fp64_sum)
-        run_gemm<MODE, T, T, 2>(F.m2l, opa, opb, nn, ld, n_rhs, in, dn_chk, true, s, ps, amax);
+        run_gemm<MODE, T, T, 2>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
       else
-        run_gemm<MODE, T, T, 1>(F.m2l, opa, opb, nn, ld, n_rhs, in, dn_chk, true, s, ps, amax);
+        run_gemm<MODE, T, T, 1>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
     };
     const void* op32 = check_form ? static_cast<const void*>(O.m2lc32) : static_cast<const void*>(O.m2l32);
-    const void* oph = check_form ? O.m2lc_hh : O.m2l_hh;
-    const void* opl = check_form ? O.m2lc_hl : O.m2l_hl;
+    const void* oph = check_form ? O.m2lc_h : O.m2l_h;
     if (prec == KIFMM_FP64) {
-      run_gemm<GM_F64, T, T, 1>(F.m2l, O.m2l64, nullptr, nn, ld, n_rhs, m2l_in, dn_chk, true, s, ps);
+      run_gemm<GM_F64, T, T, 1>(F.m2l, O.m2l64, nn, ld, F.nbox, n_rhs, m2l_in, dn_chk, true, s, ps);
     } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
-      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, nullptr, m2l_in, nullptr);
+      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, m2l_in, nullptr);
     } else if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) {
       scale16();
-      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, opl, m2l_in, W.absmax);
+      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, m2l_in, W.absmax);
     } else if constexpr (sizeof(T) == 4) {
       if (prec == KIFMM_M2L_BF16X3)
-        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_bh, O.m2l_bl, up_eq, nullptr);
+        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_b, up_eq, nullptr);
       else
-        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_bh, O.m2l_bl, up_eq, nullptr);
+        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, up_eq, nullptr);
     }
   }
   for (int l = 2; l <= F.depth; ++l) {
     if (l >= 3) {
       PhaseScope ps(PH_L2L, s);
-      run_gemm<GF, T, T>(F.l2l[l], l2l, nullptr, nn, ld, n_rhs, dn_eq, dn_chk, true, s, ps);
+      run_gemm<GF, T, T>(F.l2l[l], l2l, nn, ld, F.nbox, n_rhs, dn_eq, dn_chk, true, s, ps);
     }
     {
       PhaseScope ps(PH_DC2E, s);
-      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e, nullptr, 0, ld, n_rhs, dn_chk, dn_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e, 0, ld, F.nbox, n_rhs, dn_chk, dn_eq, false, s, ps);
     }
   }
   {
