@@ -99,6 +99,8 @@ struct DevForest {
   int32_t n_p2m = 0, n_leaf = 0, n_x = 0;
   int64_t max_src_per_prob = 0, max_tgt_per_prob = 0;
   std::vector<DevPlan> m2m, uc2e, l2l, dc2e;
+  std::vector<int32_t*> m2m_sum;     // per level [n][9], see HostForest
+  std::vector<int32_t> n_m2m_sum;
   DevPlan m2l;
   std::vector<void*> allocs;
   std::map<std::pair<int, int>, DevWork*> work;  // (fp64, n_rhs)
@@ -203,6 +205,10 @@ static DevForest* upload_forest(const HostForest& F, int n) {
     D->x_off = dev_upload<int32_t>(A, F.x_off);
     D->x_items = dev_upload<int32_t>(A, F.x_items);
     for (auto& p : F.m2m) D->m2m.push_back(upload_plan(A, p, F.nbox));
+    for (auto& t : F.m2m_sum) {
+      D->m2m_sum.push_back(t.empty() ? nullptr : dev_upload<int32_t>(A, t));
+      D->n_m2m_sum.push_back(int32_t(t.size() / 9));
+    }
     for (auto& p : F.uc2e) D->uc2e.push_back(upload_plan(A, p, F.nbox));
     for (auto& p : F.l2l) D->l2l.push_back(upload_plan(A, p, F.nbox));
     for (auto& p : F.dc2e) D->dc2e.push_back(upload_plan(A, p, F.nbox));
@@ -366,9 +372,13 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
 // profiling: HIP events around each phase on the evaluation stream
 // ------------------------------------------------------------------------
 
-enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L, PH_L2L, PH_DC2E, PH_NEAR, PH_FAR,
-             PH_SCATTER, PH_N };
-static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l", "m2l",
+// Phases hold only their own launches (the M2L phase is the gathered GEMM
+// alone; the FP16 density scaling it needs is "m2l_scale").  While profiling
+// is on, the near field runs on the evaluation stream instead of the
+// auxiliary one, so no two phases overlap and each one's events time it alone.
+enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L_SCALE, PH_M2L, PH_L2L, PH_DC2E,
+             PH_NEAR, PH_FAR, PH_SCATTER, PH_N };
+static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l", "m2l_scale", "m2l",
                                         "l2l", "dc2e", "near", "far", "scatter"};
 
 struct Profiler {
@@ -479,6 +489,20 @@ __global__ void scatter_kernel(PtrPack out, int prob0, const int64_t* __restrict
   for (int r = 0; r < n_rhs; ++r) dst[int64_t(r) * nk + ci] = TO(pot[int64_t(r) * ntgt + i]);
 }
 
+// Block-wide maximum of m (>= 0), then one atomic per block: atomics from
+// every wave onto the single result word serialize in L2.
+__device__ inline void block_max_to(float m, unsigned* out) {
+  __shared__ float s_m[16];
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) s_m[w] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < nw; ++i) m = fmaxf(m, s_m[i]);
+    atomicMax(out, __float_as_uint(m));
+  }
+}
+
 // Largest |x| over n4 float4 values, into *out as float bits (all values >= 0,
 // so unsigned order equals float order); *out must start at 0.
 __global__ void absmax_kernel(const float4* __restrict__ p, int64_t n4, unsigned* __restrict__ out) {
@@ -487,8 +511,7 @@ __global__ void absmax_kernel(const float4* __restrict__ p, int64_t n4, unsigned
     float4 v = p[i];
     m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
   }
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  block_max_to(m, out);
 }
 
 __global__ void absmax_kernel64(const double2* __restrict__ p, int64_t n2, unsigned* __restrict__ out) {
@@ -497,8 +520,39 @@ __global__ void absmax_kernel64(const double2* __restrict__ p, int64_t n2, unsig
     double2 v = p[i];
     m = fmaxf(m, float(fmax(fabs(v.x), fabs(v.y))));
   }
-  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+  block_max_to(m, out);
+}
+
+// M2M, second half: the upward check potential of each parent is the sum of
+// its children's contributions (written per child by the gathered GEMM),
+// added in octant order.  tab is [npar][9]: parent, children 0..7 or -1.
+// Columns are ld elements, ld a multiple of 32, so 16-byte units tile them.
+template <class T>
+__global__ void m2m_sum_kernel(const int32_t* __restrict__ tab, int npar, int64_t units_per_box,
+                               const uint4* __restrict__ part, uint4* __restrict__ out) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(npar) * units_per_box) return;
+  const int64_t k = i / units_per_box, u = i - k * units_per_box;
+  const int32_t* t = tab + 9 * k;
+  constexpr int E = 16 / sizeof(T);
+  T acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = T(0);
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const int c = t[1 + o];
+    if (c >= 0) {
+      const uint4 v = part[int64_t(c) * units_per_box + u];
+      const T* x = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int e = 0; e < E; ++e) acc[e] += x[e];
+    }
+  }
+  uint4 r;
+  T* y = reinterpret_cast<T*>(&r);
+#pragma unroll
+  for (int e = 0; e < E; ++e) y[e] = acc[e];
+  out[int64_t(t[0]) * units_per_box + u] = r;
 }
 
 __global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
@@ -1375,14 +1429,15 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     // auxiliary stream while the multipole passes run on s
     HIPCHECK(hipEventRecord(aux.forked, s));
     HIPCHECK(hipStreamWaitEvent(aux.stream, aux.forked, 0));
-    PhaseScope ps(PH_NEAR, aux.stream);
+    const hipStream_t ns = g_prof.on ? s : aux.stream;
+    PhaseScope ps(PH_NEAR, ns);
     P2PArgs<T> a = base;
     a.work = F.leaf_boxes;
     a.l1_off = F.u_off;
     a.l1_items = F.u_items;
     a.l2_off = F.w_off;
     a.l2_items = F.w_items;
-    run_p2p_rc<T, MODE_NEAR, 32>(a, F.n_leaf, n_rhs, false, aux.stream, ps);
+    run_p2p_rc<T, MODE_NEAR, 32>(a, F.n_leaf, n_rhs, false, ns, ps);
   }
   HIPCHECK(hipEventRecord(aux.joined, aux.stream));
   {
@@ -1395,7 +1450,19 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   for (int l = F.depth; l >= 2; --l) {
     {
       PhaseScope ps(PH_M2M, s);
-      run_gemm<GF, T, T>(F.m2m[l], m2m, nn, ld, F.nbox, n_rhs, up_eq, up_chk, false, s, ps);
+      // per-child contributions into the (not yet used) downward check
+      // columns, then the per-parent sums into the upward check potentials
+      run_gemm<GF, T, T>(F.m2m[l], m2m, nn, ld, F.nbox, n_rhs, up_eq, dn_chk, false, s, ps);
+      const int npar = F.n_m2m_sum[l];
+      if (npar > 0) {
+        const int64_t upb = int64_t(n_rhs) * ld * int64_t(sizeof(T)) / 16;
+        const int64_t tot = npar * upb;
+        hipLaunchKernelGGL(m2m_sum_kernel<T>, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, s,
+                           F.m2m_sum[l], npar, upb, reinterpret_cast<const uint4*>(dn_chk),
+                           reinterpret_cast<uint4*>(up_chk));
+        LAUNCHCHECK("m2m_sum_kernel");
+        ps.launches++;
+      }
     }
     {
       PhaseScope ps(PH_UC2E, s);
@@ -1416,21 +1483,23 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, false, s, ps);
   }
   {
-    PhaseScope ps(PH_M2L, s);
     // operand of M2L: upward densities, or (check form) upward check potentials
     const T* m2l_in = check_form ? up_chk : up_eq;
     auto scale16 = [&]() {
+      PhaseScope ps(PH_M2L_SCALE, s);
       hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint4*>(W.absmax), int64_t(1));
       LAUNCHCHECK("zero_kernel");
       if constexpr (sizeof(T) == 8)
-        hipLaunchKernelGGL(absmax_kernel64, dim3(1024), dim3(256), 0, s,
+        hipLaunchKernelGGL(absmax_kernel64, dim3(512), dim3(256), 0, s,
                            reinterpret_cast<const double2*>(m2l_in), int64_t(W.col_bytes / 16), W.absmax);
       else
-        hipLaunchKernelGGL(absmax_kernel, dim3(1024), dim3(256), 0, s,
+        hipLaunchKernelGGL(absmax_kernel, dim3(512), dim3(256), 0, s,
                            reinterpret_cast<const float4*>(m2l_in), int64_t(W.col_bytes / 16), W.absmax);
       LAUNCHCHECK("absmax_kernel");
       ps.launches += 2;
     };
+    if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) scale16();
+    PhaseScope ps(PH_M2L, s);
     const bool fp64_sum = O.p >= g_m2l_fp64_sum_min_p;
     auto run_m2l_impl = [&](auto mode_tag, const void* opa, const T* in, const unsigned* amax) {
       constexpr int MODE = decltype(mode_tag)::value;
@@ -1447,7 +1516,6 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
       run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, m2l_in, nullptr);
     } else if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) {
-      scale16();
       run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, m2l_in, W.absmax);
     } else if constexpr (sizeof(T) == 4) {
       if (prec == KIFMM_M2L_BF16X3)

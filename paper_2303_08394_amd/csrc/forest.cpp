@@ -156,12 +156,13 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
   // plans
   const int D = F.depth;
   F.m2m.assign(D + 1, new_plan(TB));
+  F.m2m_sum.assign(D + 1, {});
   F.uc2e.assign(D + 1, new_plan(TB));
   F.l2l.assign(D + 1, new_plan(TB));
   F.dc2e.assign(D + 1, new_plan(TB));
   F.m2l = new_plan(TBm);
   for (int l = 2; l <= D; ++l) {
-    // M2M: non-leaf parents with sources; step o takes the child of octant o
+    // M2M: per-child contributions, then a per-parent sum in octant order
     std::vector<int32_t> parents, withsrc, withtgt;
     for (int32_t g : lvl_boxes[l]) {
       if (nsrc_of(g) > 0) withsrc.push_back(g);
@@ -169,29 +170,22 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       if (!F.box_leaf[g] && nsrc_of(g) > 0) parents.push_back(g);
     }
     if (!parents.empty()) {
-      // child of octant o of each parent, in a lookup by (parent, octant)
+      // children with sources of the non-leaf parents of this level
       std::map<std::pair<int32_t, int>, int32_t> child;
+      std::vector<int32_t> kids;
       for (int32_t g : lvl_boxes[l + 1 <= D ? l + 1 : l])
-        if (l + 1 <= D && nsrc_of(g) > 0) child[{F.box_parent[g], F.box_octant[g]}] = g;
-      for (auto& tile : group_tiles(parents, TB, [](int32_t) { return int64_t(0); })) {
-        std::vector<int32_t> opl;
-        std::vector<std::vector<int32_t>> srcs;
-        for (int o = 0; o < 8; ++o) {
-          std::vector<int32_t> s(tile.size(), -1);
-          bool any = false;
-          for (size_t j = 0; j < tile.size(); ++j) {
-            auto it = child.find({tile[j], o});
-            if (it != child.end()) {
-              s[j] = it->second;
-              any = true;
-            }
-          }
-          if (any) {
-            opl.push_back(o);
-            srcs.push_back(s);
-          }
+        if (l + 1 <= D && nsrc_of(g) > 0) {
+          child[{F.box_parent[g], F.box_octant[g]}] = g;
+          kids.push_back(g);
         }
-        add_tile(F.m2m[l], tile, opl, srcs);
+      for (auto& tile : group_tiles(kids, TB, [&](int32_t g) { return int64_t(F.box_octant[g]); }))
+        add_tile(F.m2m[l], tile, {F.box_octant[tile[0]]}, {tile});
+      for (int32_t par : parents) {
+        F.m2m_sum[l].push_back(par);
+        for (int o = 0; o < 8; ++o) {
+          auto it = child.find({par, o});
+          F.m2m_sum[l].push_back(it != child.end() ? it->second : -1);
+        }
       }
     }
     for (auto& tile : group_tiles(withsrc, TB, [](int32_t) { return int64_t(0); }))

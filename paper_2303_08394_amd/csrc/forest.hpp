@@ -47,8 +47,13 @@ struct HostForest {
   std::vector<int32_t> leaf_boxes;  // leaves holding targets
   std::vector<int32_t> u_off, u_items, w_off, w_items;  // CSR over leaf_boxes
   std::vector<int32_t> x_boxes, x_off, x_items;         // boxes with a non-empty X list
-  // per-level plans (index = level) and the all-level M2L plan
+  // per-level plans (index = level) and the all-level M2L plan.  The M2M
+  // plan of level l has one step per child (at level l + 1, tiled by octant):
+  // it writes that child's contribution M2M[octant] * up_eq[child] to the
+  // child's own column of a scratch buffer, and m2m_sum[l] ([nparent][9]:
+  // parent, then its child of octant 0..7 or -1) adds them up per parent.
   std::vector<Plan> m2m, uc2e, l2l, dc2e;
+  std::vector<std::vector<int32_t>> m2m_sum;
   Plan m2l;
   // statistics of the lists (for work counts)
   int64_t n_u_pairs = 0, n_v_pairs = 0, n_w_pairs = 0, n_x_pairs = 0;
