@@ -152,6 +152,8 @@ static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P, int32_t ze
   d.TB = P.TB;
   d.nstep = P.nstep();
   d.useful_pairs = P.useful_pairs;
+  for (int32_t t = 0; t < P.ntile; ++t)
+    d.max_tile_steps = std::max(d.max_tile_steps, P.step_beg[t + 1] - P.step_beg[t]);
   if (P.ntile == 0) return d;
   d.tile_cols = dev_upload<int32_t>(allocs, P.tile_cols);
   d.step_beg = dev_upload<int32_t>(allocs, P.step_beg);
@@ -961,6 +963,7 @@ struct GemmArgs {
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
+constexpr int kMaxTileSteps = 320;  // >= 316, the M2L offsets a tile can hold
 
 template <int MODE, class TI, class TO, int CB>
 struct GemmCfg {
@@ -969,7 +972,11 @@ struct GemmCfg {
   static constexpr int KC = G::KC, NB = G::NB, TC = 64 * CB;
   static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3) ? 2 : 1;  // operator tables
   // per buffer: NA operator tiles [ROWS][KC] and NB column tiles [TC][KC] of TA
-  static constexpr int A_ELEMS = NA * kROWS * KC, B_ELEMS = NB * TC * KC;
+  // operator part tables sit A_TSTRIDE elements apart: 128 bytes more than a
+  // multiple of 256, so the two parts of one row land in different banks
+  static constexpr int A_TSTRIDE = kROWS * KC + (NA > 1 ? 128 / int(sizeof(TA)) : 0);
+  static constexpr int B_TSTRIDE = TC * KC + (NB > 1 ? 128 / int(sizeof(TA)) : 0);  // likewise
+  static constexpr int A_ELEMS = NA * A_TSTRIDE, B_ELEMS = NB * B_TSTRIDE;
   static constexpr int BUF_BYTES = (A_ELEMS + B_ELEMS) * int(sizeof(TA));
   // 16-byte global units per chunk
   static constexpr int A_UNITS_ROW = KC * int(sizeof(TA)) / 16;         // per table row
@@ -979,12 +986,18 @@ struct GemmCfg {
   static constexpr int B_UNITS = TC * B_UNITS_COL;
   static constexpr int B_PER_T = (B_UNITS + 255) / 256;
   // LDS rows are KC elements with no padding; the 16-byte chunks of a row are
-  // XOR-swizzled so that a chunk column of consecutive rows (a fragment read,
-  // or a staging store) falls into distinct banks.
+  // XOR-swizzled so that one chunk column of consecutive rows (a fragment
+  // read: lane = row) and the staging stores avoid bank conflicts.  Both
+  // patterns were chosen by measurement (LDS bank-conflict counter at zero):
+  // 64-byte rows: chunk ^ ((row / 2) mod 4); 128-byte rows: chunk ^ h(row)
+  // with h a bijection of row mod 8 that also separates rows r and r + 8.
   static constexpr int EPC = 16 / int(sizeof(TA));            // elements per chunk
   static constexpr int CPR = KC * int(sizeof(TA)) / 16;       // chunks per row
-  static constexpr int RPW = 128 / (KC * int(sizeof(TA)));    // rows per 128-byte bank window
-  __device__ static int swz(int row, int chunk) { return chunk ^ ((row / RPW) & (CPR - 1)); }
+  static_assert(CPR == 4 || CPR == 8, "LDS rows of 64 or 128 bytes");
+  __device__ static int swz(int row, int chunk) {
+    if constexpr (CPR == 4) return chunk ^ ((row >> 1) & 3);
+    else return chunk ^ (((row ^ (row >> 3)) & 1) | (row & 6));
+  }
   __device__ static int off(int row, int chunk) { return row * KC + swz(row, chunk) * EPC; }
 };
 
@@ -1029,6 +1042,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   constexpr int KC = Cfg::KC, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
   constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
   __shared__ __align__(16) unsigned char smem[2 * Cfg::BUF_BYTES];
+  __shared__ int s_ops[kMaxTileSteps];  // the tile's operator indices
   // FP16 split: exact power-of-two scaling of the densities into range
   float in_scale = 1.0f, out_scale = 1.0f;
   if constexpr (MODE == GM_H3) {
@@ -1077,9 +1091,9 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   }
 
   // registers of the chunk in flight from global memory
-  u32x4 ra[Cfg::A_PER_T], rb[Cfg::B_PER_T];
-  int64_t bcol[Cfg::B_PER_T];
-  int cur_step = -1;
+  // two register sets: chunk c is loaded into set c % 2 two chunks before
+  // it is computed, and moved to LDS one chunk before
+  u32x4 ra[2][Cfg::A_PER_T], rb[2][Cfg::B_PER_T];
 
   // Per-thread staging addresses, fixed for the whole tile: operator units
   // (row, part, split part) and the LDS slots they land in.  Operator rows
@@ -1089,50 +1103,79 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   int a_goff[Cfg::A_PER_T], a_loff[Cfg::A_PER_T];
 #pragma unroll
   for (int j = 0; j < Cfg::A_PER_T; ++j) {
+    // consecutive lanes: the chunks of a row, then the next row, then the
+    // next part table, then the next pair of rows
     const int u = tid + j * 256;
-    const int rl = u / (NA * Cfg::CPR), t = (u / Cfg::CPR) % NA, part = u % Cfg::CPR;
+    const int part = u % Cfg::CPR, rsub = (u / Cfg::CPR) & 1, t = (u / (2 * Cfg::CPR)) % NA;
+    const int rl = (u / (2 * Cfg::CPR * NA)) * 2 + rsub;
     const int rg = min(row0 + rl, ld - 1);
     a_goff[j] = (rg * NA + t) * ld + part * Cfg::EPC;
-    a_loff[j] = t * kROWS * KC + Cfg::off(rl, part);
+    a_loff[j] = t * Cfg::A_TSTRIDE + Cfg::off(rl, part);
   }
-  int b_goff[Cfg::B_PER_T];
-  const int zero_col = a.zero_box * a.n_rhs;  // an all-zero column for empty slots
-
-  auto load_regs = [&](int ch) __attribute__((always_inline)) {
-    const int st = sb + ch / kcs;
-    const int k0 = (ch % kcs) * KC;
-    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(a.step_op[st]) * a.op_stride + k0;
+  // Step bookkeeping of the chunk being loaded: its step, its chunk within
+  // the step, and the step's operator and source columns.  The operator
+  // index and the source boxes of the following step are fetched a whole
+  // step ahead (the tile's operator list sits in LDS), so no load latency is
+  // exposed when the step changes.  Slots past the tile's columns read the
+  // all-zero box.
+  int ld_st = sb, ld_kc = 0;
+  int cur_op = 0, nxt_op = 0;
+  int nxt_src[Cfg::B_PER_T], b_goff[Cfg::B_PER_T];
+  // The prefetch loads are unconditional (indices clamped into the tile, a
+  // step past the end re-reads the last one) so that they land directly in
+  // the registers that carry them to the next step; slots past the tile's
+  // columns are replaced by the zero box where the value is used.
+  auto fetch_step = [&](int st) __attribute__((always_inline)) {
+    const int sc = min(st, se - 1);
+    nxt_op = s_ops[sc - sb];
 #pragma unroll
-    for (int j = 0; j < Cfg::A_PER_T; ++j) ra[j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
-    if (st != cur_step) {
-      // source columns of this thread's B units for the new step
-      cur_step = st;
-#pragma unroll
-      for (int j = 0; j < Cfg::B_PER_T; ++j) {
-        const int u = tid + j * 256;
-        const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
-        int col = zero_col;
-        if (s < ncols) col = a.step_src[int64_t(st) * a.TB + s / a.n_rhs] * a.n_rhs + s % a.n_rhs;
-        b_goff[j] = col * ld + part * (16 / int(sizeof(TI)));
-      }
+    for (int j = 0; j < Cfg::B_PER_T; ++j) {
+      const int s = (tid + j * 256) / Cfg::B_UNITS_COL;
+      nxt_src[j] = a.step_src[int64_t(sc) * a.TB + min(s / a.n_rhs, a.TB - 1)];
     }
+  };
+  auto begin_step = [&]() __attribute__((always_inline)) {
+    cur_op = nxt_op;
+#pragma unroll
+    for (int j = 0; j < Cfg::B_PER_T; ++j) {
+      const int u = tid + j * 256;
+      const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
+      const int box = s < ncols ? nxt_src[j] : a.zero_box;
+      b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld + part * (16 / int(sizeof(TI)));
+    }
+  };
+  auto load_regs = [&](auto P) __attribute__((always_inline)) {
+    constexpr int R = decltype(P)::value;
+    const int k0 = ld_kc * KC;
+    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + k0;
+#pragma unroll
+    for (int j = 0; j < Cfg::A_PER_T; ++j) ra[R][j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
     const TI* inb = static_cast<const TI*>(a.in) + k0;
 #pragma unroll
-    for (int j = 0; j < Cfg::B_PER_T; ++j) rb[j] = *reinterpret_cast<const u32x4*>(inb + b_goff[j]);
+    for (int j = 0; j < Cfg::B_PER_T; ++j) rb[R][j] = *reinterpret_cast<const u32x4*>(inb + b_goff[j]);
+  };
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++ld_kc == kcs) {
+      ld_kc = 0;
+      ++ld_st;
+      begin_step();
+      fetch_step(ld_st + 1);
+    }
   };
 
-  auto store_lds = [&](int buf) __attribute__((always_inline)) {
+  auto store_lds = [&](auto P, int buf) __attribute__((always_inline)) {
+    constexpr int R = decltype(P)::value;
     TA* As = reinterpret_cast<TA*>(smem + buf * Cfg::BUF_BYTES);
     TA* Bs = As + Cfg::A_ELEMS;
 #pragma unroll
-    for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[j];
+    for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[R][j];
     constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
       const int u = tid + j * 256;
       {
         const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
-        const TI* vals = reinterpret_cast<const TI*>(&rb[j]);
+        const TI* vals = reinterpret_cast<const TI*>(&rb[R][j]);
         // input unit `part` holds k = part*EPU .. part*EPU + EPU - 1
         constexpr int EPC = Cfg::EPC;
         if constexpr (EPU >= EPC) {
@@ -1142,7 +1185,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
             const int chunk = part * (EPU / EPC) + q;
             if constexpr (BF) {
               TA* h = Bs + Cfg::off(s, chunk);
-              split_store<TA, NB, TI, EPC>(h, h + TC * KC, h + (NB - 1) * TC * KC, vals + q * EPC, in_scale);
+              split_store<TA, NB, TI, EPC>(h, h + Cfg::B_TSTRIDE, h + (NB - 1) * Cfg::B_TSTRIDE, vals + q * EPC, in_scale);
             } else {
               TA* d = Bs + Cfg::off(s, chunk);
 #pragma unroll
@@ -1154,7 +1197,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
           const int k0 = part * EPU;
           TA* d = Bs + Cfg::off(s, k0 / EPC) + k0 % EPC;
           if constexpr (BF) {
-            split_store<TA, NB, TI, EPU>(d, d + TC * KC, d + (NB - 1) * TC * KC, vals, in_scale);
+            split_store<TA, NB, TI, EPU>(d, d + Cfg::B_TSTRIDE, d + (NB - 1) * Cfg::B_TSTRIDE, vals, in_scale);
           } else {
 #pragma unroll
             for (int x = 0; x < EPU; ++x) d[x] = TA(vals[x]);
@@ -1219,14 +1262,14 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
         const int col = wc * 16 * CBW + c * 16 + r16;
         const int o = Cfg::off(col, g);
         bh[c] = *reinterpret_cast<const vec8*>(Bs + o);
-        bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * TC * KC + o);
-        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + TC * KC + o);
+        bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * Cfg::B_TSTRIDE + o);
+        if constexpr (NB == 3) bm[c] = *reinterpret_cast<const vec8*>(Bs + Cfg::B_TSTRIDE + o);
       }
 #pragma unroll
       for (int i = 0; i < RBW; ++i) {
         const int o = Cfg::off((wr * RBW + i) * 16 + r16, g);
         const vec8 ah = *reinterpret_cast<const vec8*>(As + o);
-        const vec8 al = *reinterpret_cast<const vec8*>(As + kROWS * KC + o);
+        const vec8 al = *reinterpret_cast<const vec8*>(As + Cfg::A_TSTRIDE + o);
 #pragma unroll
         for (int c = 0; c < CBW; ++c) {
           acc[i][c] = mma(ah, bh[c], acc[i][c]);
@@ -1239,35 +1282,80 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
         }
       }
     }
+    // keep the staging of later chunks (which waits for their global loads)
+    // behind this chunk's matrix instructions
+    __builtin_amdgcn_sched_barrier(0);
   };
 
-  auto flush = [&](int ch) __attribute__((always_inline)) {
+  auto flush = [&]() __attribute__((always_inline)) {
     if constexpr (FLUSH) {
-      if ((ch + 1) % kcs == 0) {
 #pragma unroll
-        for (int i = 0; i < RBW; ++i)
+      for (int i = 0; i < RBW; ++i)
 #pragma unroll
-          for (int c = 0; c < CBW; ++c)
+        for (int c = 0; c < CBW; ++c)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              acc64[i][c][v] += double(acc[i][c][v]);
-              acc[i][c][v] = 0;
-            }
-      }
+          for (int v = 0; v < 4; ++v) {
+            acc64[i][c][v] += double(acc[i][c][v]);
+            acc[i][c][v] = 0;
+          }
     }
   };
 
   if (nchunks > 0) {
-    load_regs(0);
-    store_lds(0);
+    for (int i = tid; i < se - sb; i += 256) s_ops[i] = a.step_op[sb + i];
     __syncthreads();
-    for (int ch = 0; ch < nchunks; ++ch) {
-      const int buf = ch & 1;
-      if (ch + 1 < nchunks) load_regs(ch + 1);
-      compute(buf);
-      flush(ch);
-      if (ch + 1 < nchunks) store_lds(buf ^ 1);
+    fetch_step(sb);
+    begin_step();
+    fetch_step(sb + 1);
+    const std::integral_constant<int, 0> R0;
+    const std::integral_constant<int, 1> R1;
+    auto issue = [&](auto P) __attribute__((always_inline)) {  // the next chunk in order
+      advance();
+      load_regs(P);
+    };
+    int cm_kc = 0;  // chunk within the step, on the compute side
+    auto step_end = [&]() __attribute__((always_inline)) {
+      if (++cm_kc == kcs) {
+        cm_kc = 0;
+        flush();
+      }
+    };
+    load_regs(R0);
+    store_lds(R0, 0);
+    if (nchunks > 1) issue(R1);
+    __syncthreads();
+    // Chunk c is computed from LDS buffer c % 2; while it is, chunk c + 2 is
+    // loaded into register set c % 2 and chunk c + 1 moves from set
+    // (c + 1) % 2 into the other buffer.  The loop runs two chunks at a time
+    // with no branches around loads and stores; the last one to three chunks
+    // follow it.
+    int ch = 0;
+    for (; ch + 3 < nchunks; ch += 2) {
+      issue(R0);
+      compute(0);
+      step_end();
+      store_lds(R1, 1);
       __syncthreads();
+      issue(R1);
+      compute(1);
+      step_end();
+      store_lds(R0, 0);
+      __syncthreads();
+    }
+    if (ch + 2 < nchunks) issue(R0);
+    compute(0);
+    step_end();
+    if (ch + 1 < nchunks) {
+      store_lds(R1, 1);
+      __syncthreads();
+      compute(1);
+      step_end();
+      if (ch + 2 < nchunks) {
+        store_lds(R0, 0);
+        __syncthreads();
+        compute(0);
+        step_end();
+      }
     }
   }
 
@@ -1315,6 +1403,7 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   const int ncols = P.TB * n_rhs;
   if (ncols > 128) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
+  if (P.max_tile_steps > kMaxTileSteps) raise(KIFMM_EUNSUPPORTED, "GEMM tile with too many operator steps");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
