@@ -271,18 +271,27 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       }
       tiles.swap(order);
     }
+    // Step order inside a tile: by the parity of the offset, then by
+    // operator.  The targets of one tile share their octant, so the parity of
+    // the offset fixes the parity class of every source box the step reads;
+    // the blocks on one XCD then sweep one class (1/8 of the level's
+    // densities) after another and find them in that XCD's L2.
+    auto step_key = [&](int32_t op) {
+      const int32_t* d = &ops.m2l_offset[3 * size_t(op)];
+      return int32_t((((d[0] & 1) << 2) | ((d[1] & 1) << 1) | (d[2] & 1)) * kNumM2L + op);
+    };
     for (auto& tile : tiles) {
-      std::map<int32_t, std::vector<int32_t>> steps;
+      std::map<int32_t, std::vector<int32_t>> steps;  // keyed by step_key
       for (size_t j = 0; j < tile.size(); ++j)
         for (auto& e : vl[tile[j]]) {
-          auto& s = steps[e.first];
+          auto& s = steps[step_key(e.first)];
           if (s.empty()) s.assign(tile.size(), -1);
           s[j] = e.second;
         }
       std::vector<int32_t> opl;
       std::vector<std::vector<int32_t>> srcs;
       for (auto& s : steps) {
-        opl.push_back(s.first);
+        opl.push_back(s.first % kNumM2L);
         srcs.push_back(s.second);
       }
       add_tile(F.m2l, tile, opl, srcs);
