@@ -269,7 +269,9 @@ void set_m2l_check_min_p(int p) { g_m2l_check_min_p = p; }
 static int g_m2l_fp64_sum_min_p = 10;
 void set_m2l_fp64_sum_min_p(int p) { g_m2l_fp64_sum_min_p = p; }
 
-// Interleaves the high and low parts of every operator row: [k][ld][2][ld].
+// Interleaves the high and low parts of every operator row in blocks of the
+// GEMM k-chunk (32): [k][ld rows][ld / 32][2][32], so that the two parts of
+// one row's chunk are one 128-byte line.
 template <class Split>
 static uint16_t* upload_split(DevOps* O, const std::vector<double>& pad, Split split) {
   const size_t ld = size_t(O->ld), rows = pad.size() / ld;
@@ -278,8 +280,9 @@ static uint16_t* upload_split(DevOps* O, const std::vector<double>& pad, Split s
     for (size_t j = 0; j < ld; ++j) {
       uint16_t hi, lo;
       split(pad[r * ld + j], hi, lo);
-      out[(2 * r) * ld + j] = hi;
-      out[(2 * r + 1) * ld + j] = lo;
+      const size_t base = ((r * (ld / 32) + j / 32) * 2) * 32 + j % 32;
+      out[base] = hi;
+      out[base + 32] = lo;
     }
   return dev_upload<uint16_t>(O->allocs, out);
 }
@@ -949,7 +952,7 @@ template <> struct GT<GM_H3> {
 };
 
 struct GemmArgs {
-  const void* ops;      // [nop][ld rows][NA parts][ld]; NA = 2 for split modes (high, low)
+  const void* ops;      // [nop][ld rows][ld / KC][NA parts][KC]; NA = 2 for split modes (high, low)
   int64_t op_stride;    // elements between operators (0: one operator)
   int ld, n_rhs, accumulate, TB;
   const void* in;       // columns [ncol][ld] of TI
@@ -1033,15 +1036,29 @@ __device__ inline void split_store(H* dst_h, H* dst_m, H* dst_l, const T* v, flo
 
 // TAG separates the M2L launches into their own symbols: 1 = M2L, 2 = M2L
 // with FP32 sums moved into FP64 registers after every operator step.
+// LDS buffering of the gathered GEMM.  Two buffers let one chunk be staged
+// while the previous one is read (one barrier per chunk); one buffer costs a
+// second barrier per chunk but halves the LDS, so three blocks fit on a CU.
+// One buffer where the registers allow three blocks (32-bit operands, no
+// FP64 sums): measured faster there, as the staging latency is what bounds
+// the split-precision M2L.
+template <int MODE, class TI, int TAG>
+struct GemmOcc {
+  static constexpr bool THREE = TAG != 2 && MODE != GM_F64 && sizeof(TI) == 4;
+  static constexpr int NBUF = THREE ? 1 : 2;
+  static constexpr int MINB = THREE ? 3 : 2;
+};
+
 template <int MODE, class TI, class TO, int CB, int TAG>
-__global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
+__global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kernel(GemmArgs a) {
   using Cfg = GemmCfg<MODE, TI, TO, CB>;
   using G = GT<MODE>;
   using TA = typename Cfg::TA;
   using ACC = typename G::acc;
   constexpr int KC = Cfg::KC, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
   constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
-  __shared__ __align__(16) unsigned char smem[2 * Cfg::BUF_BYTES];
+  constexpr int NBUF = GemmOcc<MODE, TI, TAG>::NBUF;
+  __shared__ __align__(16) unsigned char smem[NBUF * Cfg::BUF_BYTES];
   __shared__ int s_ops[kMaxTileSteps];  // the tile's operator indices
   // FP16 split: exact power-of-two scaling of the densities into range
   float in_scale = 1.0f, out_scale = 1.0f;
@@ -1100,6 +1117,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   // past ld are clamped to a valid row: they only feed output rows that the
   // epilogue discards.
   static_assert(Cfg::A_UNITS % 256 == 0 && Cfg::B_UNITS % 256 == 0, "staging units per thread");
+  static_assert(NA == 1 || KC == 32, "split operator tables are interleaved in blocks of 32");
   int a_goff[Cfg::A_PER_T], a_loff[Cfg::A_PER_T];
 #pragma unroll
   for (int j = 0; j < Cfg::A_PER_T; ++j) {
@@ -1109,7 +1127,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     const int part = u % Cfg::CPR, rsub = (u / Cfg::CPR) & 1, t = (u / (2 * Cfg::CPR)) % NA;
     const int rl = (u / (2 * Cfg::CPR * NA)) * 2 + rsub;
     const int rg = min(row0 + rl, ld - 1);
-    a_goff[j] = (rg * NA + t) * ld + part * Cfg::EPC;
+    a_goff[j] = rg * ld * NA + t * KC + part * Cfg::EPC;
     a_loff[j] = t * Cfg::A_TSTRIDE + Cfg::off(rl, part);
   }
   // Step bookkeeping of the chunk being loaded: its step, its chunk within
@@ -1147,7 +1165,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   auto load_regs = [&](auto P) __attribute__((always_inline)) {
     constexpr int R = decltype(P)::value;
     const int k0 = ld_kc * KC;
-    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + k0;
+    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + NA * k0;
 #pragma unroll
     for (int j = 0; j < Cfg::A_PER_T; ++j) ra[R][j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
     const TI* inb = static_cast<const TI*>(a.in) + k0;
@@ -1165,7 +1183,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
 
   auto store_lds = [&](auto P, int buf) __attribute__((always_inline)) {
     constexpr int R = decltype(P)::value;
-    TA* As = reinterpret_cast<TA*>(smem + buf * Cfg::BUF_BYTES);
+    TA* As = reinterpret_cast<TA*>(smem + (NBUF == 2 ? buf : 0) * Cfg::BUF_BYTES);
     TA* Bs = As + Cfg::A_ELEMS;
 #pragma unroll
     for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[R][j];
@@ -1208,7 +1226,7 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
   };
 
   auto compute = [&](int buf) __attribute__((always_inline)) {
-    const TA* As = reinterpret_cast<const TA*>(smem + buf * Cfg::BUF_BYTES);
+    const TA* As = reinterpret_cast<const TA*>(smem + (NBUF == 2 ? buf : 0) * Cfg::BUF_BYTES);
     const TA* Bs = As + Cfg::A_ELEMS;
     constexpr int KL = KC / 4;  // k values per lane per chunk
     if constexpr (!BF) {
@@ -1330,15 +1348,22 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     // with no branches around loads and stores; the last one to three chunks
     // follow it.
     int ch = 0;
+    // with one LDS buffer, every wave must be done reading it before the
+    // next chunk is stored
+    auto reuse = [&]() __attribute__((always_inline)) {
+      if constexpr (NBUF == 1) __syncthreads();
+    };
     for (; ch + 3 < nchunks; ch += 2) {
       issue(R0);
       compute(0);
       step_end();
+      reuse();
       store_lds(R1, 1);
       __syncthreads();
       issue(R1);
       compute(1);
       step_end();
+      reuse();
       store_lds(R0, 0);
       __syncthreads();
     }
@@ -1346,11 +1371,13 @@ __global__ __launch_bounds__(256, 2) void gemm_kernel(GemmArgs a) {
     compute(0);
     step_end();
     if (ch + 1 < nchunks) {
+      reuse();
       store_lds(R1, 1);
       __syncthreads();
       compute(1);
       step_end();
       if (ch + 2 < nchunks) {
+        reuse();
         store_lds(R0, 0);
         __syncthreads();
         compute(0);
