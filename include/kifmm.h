@@ -214,6 +214,11 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     in FP32 (FP32, BF16 and FP16 products) moves its sums
  *                     into FP64 after every operator step (default 10; 17 =
  *                     never).
+ *   "m2l_split":      1 (default): every M2L tile runs as two blocks, one for
+ *                     the offsets with even x component and one for the odd,
+ *                     both adding into the zeroed output with atomics; each
+ *                     output is then the sum of two terms, so results stay
+ *                     bitwise reproducible.  0: one block per tile.
  * EINVAL for an unknown key or value. */
 kifmm_status kifmm_set_tuning(const char* key, int32_t value);
 

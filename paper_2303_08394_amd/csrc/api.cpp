@@ -62,6 +62,11 @@ static int plan_width(int n_rhs) { return std::max(1, 64 / n_rhs); }
 // tuning (see kifmm_set_tuning)
 static std::atomic<int> g_m2l_tile_cols{64};
 static int m2l_plan_width(int n_rhs) { return std::max(1, g_m2l_tile_cols.load() / n_rhs); }
+static std::atomic<int> g_m2l_split{1};
+// a cached plan is reused only if it was cut the way the tuning asks now
+static bool plan_current(const HostForest& F, int TB, int TBm) {
+  return F.dc2e.back().TB == TB && F.m2l.TB == TBm && F.m2l.split == (g_m2l_split.load() != 0);
+}
 
 template <class F>
 static kifmm_status guard(F&& f) {
@@ -207,11 +212,10 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
     if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate: null charges or potentials");
     auto* t = const_cast<kifmm_tree*>(tree);
     const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
-    if (!t->state || t->state_n != ops->host->n || t->state->host->dc2e.back().TB != TB ||
-        t->state->host->m2l.TB != TBm) {
+    if (!t->state || t->state_n != ops->host->n || !plan_current(*t->state->host, TB, TBm)) {
       t->state.reset(new EvalState());
       const HostTree* one = t->host.get();
-      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm));
+      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0));
       t->state_n = ops->host->n;
     }
     const void* q[1] = {charges};
@@ -237,12 +241,13 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
     {
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto& slot = g_batches[key];
-      if (slot && slot->host->m2l.TB != m2l_plan_width(1)) slot.reset();
+      if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1))) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);
         for (int k = 0; k < n_prob; ++k) hts[k] = trees[k]->host.get();
         auto s = std::make_unique<EvalState>();
-        s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1)));
+        s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1),
+                                   g_m2l_split.load() != 0));
         slot = std::move(s);
       }
       st = slot.get();
@@ -267,7 +272,7 @@ kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n
       if (!std::isfinite(q[i])) raise(KIFMM_EINVAL, "evaluate_simple: non-finite charge");
     EvalState st;
     const HostTree* one = ht.get();
-    st.host.reset(build_forest(&one, 1, *ho, plan_width(1), m2l_plan_width(1)));
+    st.host.reset(build_forest(&one, 1, *ho, plan_width(1), m2l_plan_width(1), g_m2l_split.load() != 0));
     OpsCache oc;
     evaluate_simple_host(st, *ho, oc, q, n_src, pot, n_tgt);
   });
@@ -299,6 +304,11 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
   if (std::strcmp(key, "m2l_tile_cols") == 0) {
     if (value != 64 && value != 128) return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64 or 128");
     g_m2l_tile_cols = value;
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "m2l_split") == 0) {
+    if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: m2l_split must be 0 or 1");
+    g_m2l_split = value;
     return KIFMM_OK;
   }
   if (std::strcmp(key, "graph") == 0) {

@@ -17,6 +17,7 @@ struct DevPlan {
   int32_t *tile_cols = nullptr, *step_beg = nullptr, *step_op = nullptr, *step_src = nullptr;
   int64_t nstep = 0, useful_pairs = 0;
   int32_t max_tile_steps = 0;  // longest step list of one tile
+  bool atomic = false;         // tiles add into the output with atomics
 };
 
 struct DevForest;   // defined in evaluate.hip

@@ -152,6 +152,7 @@ static DevPlan upload_plan(std::vector<void*>& allocs, const Plan& P, int32_t ze
   d.TB = P.TB;
   d.nstep = P.nstep();
   d.useful_pairs = P.useful_pairs;
+  d.atomic = P.atomic;
   for (int32_t t = 0; t < P.ntile; ++t)
     d.max_tile_steps = std::max(d.max_tile_steps, P.step_beg[t + 1] - P.step_beg[t]);
   if (P.ntile == 0) return d;
@@ -378,12 +379,12 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
 // ------------------------------------------------------------------------
 
 // Phases hold only their own launches (the M2L phase is the gathered GEMM
-// alone; the FP16 density scaling it needs is "m2l_scale").  While profiling
+// alone; zeroing its output and the FP16 density scale are "m2l_prep").  While profiling
 // is on, the near field runs on the evaluation stream instead of the
 // auxiliary one, so no two phases overlap and each one's events time it alone.
-enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_P2L, PH_M2L_SCALE, PH_M2L, PH_L2L, PH_DC2E,
+enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_M2L_PREP, PH_M2L, PH_P2L, PH_L2L, PH_DC2E,
              PH_NEAR, PH_FAR, PH_SCATTER, PH_N };
-static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "p2l", "m2l_scale", "m2l",
+static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "m2l_prep", "m2l", "p2l",
                                         "l2l", "dc2e", "near", "far", "scatter"};
 
 struct Profiler {
@@ -963,6 +964,7 @@ struct GemmArgs {
   const int32_t* step_src;
   const unsigned* absmax;  // FP16 split: bits of max |input| (non-negative float)
   int zero_box;            // box index of the all-zero columns (the forest's nbox)
+  int atomic;              // add into the output with atomics (see Plan::atomic)
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
@@ -1406,8 +1408,12 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
               TAcc val = TAcc(acc[i][c][v]);
               if constexpr (FLUSH) val = TAcc(acc64[i][c][v] + double(acc[i][c][v]));
               if constexpr (MODE == GM_H3) val *= TAcc(out_scale);
-              if (a.accumulate) val += TAcc(o[row]);
-              o[row] = TO(val);
+              if (a.atomic) {
+                unsafeAtomicAdd(o + row, TO(val));
+              } else {
+                if (a.accumulate) val += TAcc(o[row]);
+                o[row] = TO(val);
+              }
             }
           }
         }
@@ -1432,7 +1438,7 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
   if (P.max_tile_steps > kMaxTileSteps) raise(KIFMM_EUNSUPPORTED, "GEMM tile with too many operator steps");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
-             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box};
+             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
   if (ncols > 64)
     hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG>), grid, dim3(256), 0, s, g);
@@ -1586,23 +1592,19 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     }
   }
   {
-    PhaseScope ps(PH_P2L, s);
-    int64_t n16 = int64_t(W.col_bytes / 16);
-    hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, static_cast<uint4*>(W.dn_chk), n16);
-    LAUNCHCHECK("zero_kernel");
-    ps.launches++;
-    P2PArgs<T> a = base;
-    a.work = F.x_boxes;
-    a.l1_off = F.x_off;
-    a.l1_items = F.x_items;
-    a.out_col = dn_chk;
-    run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, false, s, ps);
-  }
-  {
     // operand of M2L: upward densities, or (check form) upward check potentials
     const T* m2l_in = check_form ? up_chk : up_eq;
+    {
+      // M2L adds its tiles into zeroed downward check potentials with
+      // atomics (two terms at most per value); P2L and L2L add afterwards
+      PhaseScope ps(PH_M2L_PREP, s);
+      int64_t n16 = int64_t(W.col_bytes / 16);
+      hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, static_cast<uint4*>(W.dn_chk), n16);
+      LAUNCHCHECK("zero_kernel");
+      ps.launches++;
+    }
     auto scale16 = [&]() {
-      PhaseScope ps(PH_M2L_SCALE, s);
+      PhaseScope ps(PH_M2L_PREP, s);
       hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, s, reinterpret_cast<uint4*>(W.absmax), int64_t(1));
       LAUNCHCHECK("zero_kernel");
       if constexpr (sizeof(T) == 8)
@@ -1639,6 +1641,15 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       else
         run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, up_eq, nullptr);
     }
+  }
+  {
+    PhaseScope ps(PH_P2L, s);
+    P2PArgs<T> a = base;
+    a.work = F.x_boxes;
+    a.l1_off = F.x_off;
+    a.l1_items = F.x_items;
+    a.out_col = dn_chk;
+    run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, false, s, ps);
   }
   for (int l = 2; l <= F.depth; ++l) {
     if (l >= 3) {

@@ -52,7 +52,8 @@ Plan new_plan(int TB) {
 
 }  // namespace
 
-HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm) {
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
+                         bool split) {
   auto* Fp = new HostForest();
   HostForest& F = *Fp;
   F.nprob = n;
@@ -242,35 +243,6 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
     auto tiles = group_tiles(tg, TBm, [&](int32_t g) {
       return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g];
     });
-    // Launch order: blocks are dealt to the 8 XCDs round-robin, so tile t is
-    // given octant class t % 8 while every class has tiles left: the blocks
-    // resident on one XCD then walk the same operator sequence and share it
-    // through that XCD's L2.  Inside a class, tiles with more steps go first.
-    {
-      std::array<std::vector<std::vector<int32_t>>, 8> q;
-      for (auto& t : tiles) q[F.box_octant[t[0]]].push_back(t);
-      auto cost = [&](const std::vector<int32_t>& t) {
-        std::set<int32_t> ops;
-        for (int32_t g : t)
-          for (auto& e : vl[g]) ops.insert(e.first);
-        return ops.size();
-      };
-      for (auto& v : q)
-        std::stable_sort(v.begin(), v.end(), [&](const std::vector<int32_t>& x, const std::vector<int32_t>& y) {
-          return cost(x) > cost(y);
-        });
-      std::vector<std::vector<int32_t>> order;
-      std::array<size_t, 8> pos{};
-      for (bool any = true; any;) {
-        any = false;
-        for (int o = 0; o < 8; ++o)
-          if (pos[o] < q[o].size()) {
-            order.push_back(q[o][pos[o]++]);
-            any = true;
-          }
-      }
-      tiles.swap(order);
-    }
     // Step order inside a tile: by the parity of the offset, then by
     // operator.  The targets of one tile share their octant, so the parity of
     // the offset fixes the parity class of every source box the step reads;
@@ -280,6 +252,12 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       const int32_t* d = &ops.m2l_offset[3 * size_t(op)];
       return int32_t((((d[0] & 1) << 2) | ((d[1] & 1) << 1) | (d[2] & 1)) * kNumM2L + op);
     };
+    struct Part {
+      std::vector<int32_t> cols, opl;
+      std::vector<std::vector<int32_t>> srcs;
+      int cls;
+    };
+    std::array<std::vector<Part>, 8> q;  // per octant class
     for (auto& tile : tiles) {
       std::map<int32_t, std::vector<int32_t>> steps;  // keyed by step_key
       for (size_t j = 0; j < tile.size(); ++j)
@@ -288,14 +266,48 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
           if (s.empty()) s.assign(tile.size(), -1);
           s[j] = e.second;
         }
-      std::vector<int32_t> opl;
-      std::vector<std::vector<int32_t>> srcs;
+      Part whole{tile, {}, {}, F.box_octant[tile[0]]};
       for (auto& s : steps) {
-        opl.push_back(s.first % kNumM2L);
-        srcs.push_back(s.second);
+        whole.opl.push_back(s.first % kNumM2L);
+        whole.srcs.push_back(s.second);
       }
-      add_tile(F.m2l, tile, opl, srcs);
+      // The step list is cut in two parts run by two blocks (twice the
+      // blocks the level's tiles alone give); both add into the zeroed
+      // output, so each value is the sum of at most two terms and does not
+      // depend on their order.  The cut is at a fixed offset property (x
+      // offset even / odd: the first four parity classes) and every tile is
+      // cut, so a box's two partial sums do not depend on which boxes share
+      // its tile (batches and multi-RHS runs reproduce single runs bitwise).
+      const size_t ns = whole.opl.size();
+      size_t h = 0;
+      while (h < ns && step_key(whole.opl[h]) < 4 * kNumM2L) ++h;
+      if (split && h > 0 && h < ns) {
+        Part a{tile, {whole.opl.begin(), whole.opl.begin() + h}, {whole.srcs.begin(), whole.srcs.begin() + h}, whole.cls};
+        Part b{tile, {whole.opl.begin() + h, whole.opl.end()}, {whole.srcs.begin() + h, whole.srcs.end()}, whole.cls};
+        q[whole.cls].push_back(std::move(a));
+        q[whole.cls].push_back(std::move(b));
+      } else {
+        q[whole.cls].push_back(std::move(whole));
+      }
     }
+    // Launch order: blocks are dealt to the 8 XCDs round-robin, so part t is
+    // given octant class t % 8 while every class has parts left: the blocks
+    // resident on one XCD then walk the same operator sequence and share it
+    // through that XCD's L2.  Inside a class, parts with more steps go first.
+    for (auto& v : q)
+      std::stable_sort(v.begin(), v.end(), [](const Part& x, const Part& y) { return x.opl.size() > y.opl.size(); });
+    std::array<size_t, 8> pos{};
+    for (bool any = true; any;) {
+      any = false;
+      for (int o = 0; o < 8; ++o)
+        if (pos[o] < q[o].size()) {
+          Part& t = q[o][pos[o]++];
+          add_tile(F.m2l, t.cols, t.opl, t.srcs);
+          any = true;
+        }
+    }
+    F.m2l.atomic = true;
+    F.m2l.split = split;
   }
   return Fp;
 }

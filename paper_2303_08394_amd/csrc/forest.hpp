@@ -25,6 +25,10 @@ struct Plan {
   std::vector<int32_t> step_src;   // [nstep][TB]
   int64_t nstep() const { return int64_t(step_op.size()); }
   int64_t useful_pairs = 0;        // (column, step) pairs with a source
+  // Tiles add into the output with atomics instead of read-add-write; a
+  // column then appears in at most two tiles and the output starts at zero.
+  bool atomic = false;
+  bool split = false;              // tiles cut in two (plan cache key)
 };
 
 struct HostForest {
@@ -61,7 +65,9 @@ struct HostForest {
 };
 
 // Builds the forest of `n` trees for operator set `ops`: plan width TB boxes
-// per tile for M2M, L2L and the solves, TBm for M2L.
-HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm);
+// per tile for M2M, L2L and the solves, TBm for M2L.  With split, every M2L
+// tile is run as two blocks (even and odd x offsets).
+HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
+                         bool split);
 
 }  // namespace kifmm
