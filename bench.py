@@ -83,7 +83,7 @@ def _measured_traffic(precision: str):
 # three split-FP16 products with FP32 accumulation (meets the 1e-5 target at
 # p = 6 with a 4x margin; BF16x3 does not).
 DEFAULT_PRECISION = {"uniform_1m": "f16x3", "plain_20k": "fp64", "sphere_4m": "bf16x3",
-                     "batch_64": "fp32", "multi_rhs_1m": "f16x3"}
+                     "batch_64": "fp32", "multi_rhs_1m": "f16x3", "paper_sphere_1m": "f16x3"}
 
 
 def _problems(args):
@@ -99,31 +99,37 @@ def _problems(args):
         return [I.batch_problem(k) for k in range(64)]
     if args.config == "multi_rhs_1m":
         return [I.multi_rhs_1m()]
+    if args.config == "paper_sphere_1m":
+        return [I.paper_sphere_1m()]
     raise SystemExit(f"unknown config {args.config}")
 
 
 def cpu_baseline():
-    """The FP64 oracle, single-threaded, on a bounded sample of the same
-    recipe: N = 125,000 uniform-cube points with uniform depth 4 (the same
-    ~30.5 points per leaf and p = 6 as the 1M workload)."""
+    """The FP64 oracle on one BLAS thread (its fastest setting: its BLAS calls
+    are small, and 8 threads made it 3.5x slower), on a bounded sample of the
+    same recipe: N = 125,000 uniform-cube points with uniform depth 4 (the
+    same ~30.5 points per leaf and p = 6 as the 1M workload)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import kifmm as OK
     from oracle.octree import Octree
     from paper_2303_08394_amd import inputs as I
-    n = 125_000
+    n, reps = 125_000, 3
+    cores = 1
     x, q = I.uniform_cube(n, seed=0, charge_range=(-1.0, 1.0))
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=cores):
         t0 = time.perf_counter()
         tree = Octree(x, x, uniform_depth=4, center=I.UNIT_CUBE_CENTER, halfwidth=I.UNIT_CUBE_HALFWIDTH)
         fm = OK.KIFMM(tree, 6)
         t1 = time.perf_counter()
-        fm.evaluate(q[0])
+        for _ in range(reps):
+            fm.evaluate(q[0])
         t2 = time.perf_counter()
-    ev = t2 - t1
-    return {"value": n / ev / 1e6, "unit": "Mpoints/s", "cores": 1, "kind": "oracle",
+    ev = (t2 - t1) / reps
+    return {"value": n / ev / 1e6, "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle evaluate, N={n} uniform cube, depth 4 (30.5 pts/leaf), "
-                      f"p=6, one BLAS thread; evaluate {ev:.1f} s, tree+lists {t1 - t0:.1f} s"}
+                      f"p=6, {cores} BLAS thread; {reps} evaluations, {ev:.1f} s each "
+                      f"(tree+lists+operators {t1 - t0:.1f} s, not counted)"}
 
 
 def main():
@@ -132,7 +138,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="uniform_1m",
-                    choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m"])
+                    choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m",
+                             "paper_sphere_1m"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16x3", "bf16x5", "f16x3", "fp64", "fp64+m2l_fp32", "fp64+m2l_f16x3"])
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
@@ -325,6 +332,13 @@ def main():
         "precompute_s": t_ops,
         **result,
     }
+    if args.config == "paper_sphere_1m":
+        # the paper quotes mean list sizes |U|=11, |V|=42, |X|=3, |W|=3 for its tree
+        bx = tree.boxes()
+        leaves = int((bx["is_leaf"] == 1).sum())
+        lvl2 = int((bx["level"] >= 2).sum())
+        line["list_means"] = {"U": info.n_u / leaves, "V": info.n_v / lvl2, "W": info.n_w / leaves,
+                              "X": info.n_x / lvl2}
     if not args.no_cpu_baseline:
         if args.config == "uniform_1m":
             line["cpu_baseline"] = cpu_baseline()

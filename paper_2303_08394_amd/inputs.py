@@ -135,6 +135,14 @@ def multi_rhs_1m(n: int = 1_000_000, n_rhs: int = 32, depth: int = 5, p: int = 1
                    name=f"uniform_cube_n{n}_rhs{n_rhs}_p{p}_depth{depth}")
 
 
+def paper_sphere_1m(n: int = 1_000_000, ncrit: int = 150, p: int = 6) -> Problem:
+    """The paper's experiment shape: N=1M points on the unit sphere surface
+    (no radial jitter), charges [0,1), p=6, adaptive ncrit=150, root from data."""
+    x, q = sphere_surface(n, seed=0, jitter=0.0)
+    return Problem(x, q, p=p, uniform_depth=-1, ncrit=ncrit, max_depth=16,
+                   center=None, halfwidth=0.0, name=f"sphere_surface_n{n}_p{p}_ncrit{ncrit}")
+
+
 def sample_indices(n: int, k: int, seed: int = 12345) -> np.ndarray:
     """A sorted seeded subsample of k distinct indices out of n."""
     rng = np.random.default_rng(seed)
