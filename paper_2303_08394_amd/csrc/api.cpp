@@ -311,6 +311,11 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
     g_m2l_split = value;
     return KIFMM_OK;
   }
+  if (std::strcmp(key, "near_fork") == 0) {
+    if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: near_fork must be 0 or 1");
+    set_near_fork(value);
+    return KIFMM_OK;
+  }
   if (std::strcmp(key, "graph") == 0) {
     if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: graph must be 0 or 1");
     set_use_graphs(value != 0);

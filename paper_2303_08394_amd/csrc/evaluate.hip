@@ -45,6 +45,18 @@ static constexpr double kRin = 1.05, kRout = 2.95;
 // 2^e with e chosen from their largest magnitude so that it maps below 2^14.
 constexpr int kF16OpExp = 10;
 
+// Exponent e of the FP16 density scale 2^e: the largest magnitude (absmax
+// word, float bits) lands in [2^13, 2^14).
+__device__ inline int f16_density_exp(const unsigned* absmax) {
+  const float mx = __uint_as_float(*absmax);
+  int e = 0;
+  if (mx > 0.0f) {
+    (void)frexpf(mx, &e);  // mx in [2^(e-1), 2^e)
+    e = 14 - e;
+  }
+  return e;
+}
+
 // ------------------------------------------------------------------------
 // device state
 // ------------------------------------------------------------------------
@@ -78,6 +90,8 @@ struct DevWork {
   double* pot = nullptr;    // [n_rhs][ntgt]
   unsigned* absmax = nullptr;  // [4] scratch word for the FP16 density scale
   size_t col_bytes = 0;
+  void* split = nullptr;       // split-precision M2L operand, up to 3 16-bit parts per element
+  size_t split_bytes = 0;
   std::vector<void*> allocs;
   ~DevWork() {
     for (void* p : allocs) (void)hipFree(p);
@@ -372,6 +386,16 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
   W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * F.ntgt * 8));
   W->absmax = static_cast<unsigned*>(alloc_bytes(16));
   return W;
+}
+
+// The split M2L operand ([columns][ld / 32][parts][32] of 16-bit values),
+// allocated on first use by a split-precision mode (outside graph capture).
+static void ensure_split(DevForest& F, DevWork* W) {
+  if (W->split) return;
+  const size_t cols = size_t(F.nbox + 1) * W->n_rhs * F.ld;
+  W->split_bytes = cols * 3 * 2;
+  W->split = dev_alloc<unsigned char>(W->allocs, W->split_bytes);
+  HIPCHECK(hipMemset(W->split, 0, W->split_bytes));
 }
 
 // ------------------------------------------------------------------------
@@ -987,7 +1011,10 @@ struct GemmCfg {
   static constexpr int A_UNITS_ROW = KC * int(sizeof(TA)) / 16;         // per table row
   static constexpr int A_UNITS = NA * kROWS * A_UNITS_ROW;
   static constexpr int A_PER_T = (A_UNITS + 255) / 256;
-  static constexpr int B_UNITS_COL = KC * int(sizeof(TI)) / 16;
+  // split modes read densities already split into NB 16-bit parts,
+  // chunk-interleaved like the operators ([column][ld / KC][NB][KC])
+  static constexpr bool SPLIT = NA > 1;
+  static constexpr int B_UNITS_COL = SPLIT ? NB * KC * int(sizeof(TA)) / 16 : KC * int(sizeof(TI)) / 16;
   static constexpr int B_UNITS = TC * B_UNITS_COL;
   static constexpr int B_PER_T = (B_UNITS + 255) / 256;
   // LDS rows are KC elements with no padding; the 16-byte chunks of a row are
@@ -1006,34 +1033,36 @@ struct GemmCfg {
   __device__ static int off(int row, int chunk) { return row * KC + swz(row, chunk) * EPC; }
 };
 
-// Splits 4 (or 2) inputs x*scale into nb low-precision parts, written as one
-// 8-byte (4-byte) store per part.
-template <class H, int NB, class T, int CNT>
-__device__ inline void split_store(H* dst_h, H* dst_m, H* dst_l, const T* v, float scale) {
-  H h[CNT], m[CNT], l[CNT];
+// The M2L operand of the split modes: every density x (times 2^e for FP16,
+// from the absmax word) becomes NB low-precision parts h = H(x),
+// m = H(x - h), l = H(x - h - m), stored like the operator tables: element
+// k of column c, part t at c*ld*NB + (k/32)*NB*32 + t*32 + k%32.  One thread
+// converts 8 consecutive elements of a column (a 16-byte chunk per part).
+template <class T, class H, int NB>
+__global__ void split_kernel(const T* __restrict__ in, H* __restrict__ out, int64_t ngroups, int ld,
+                             const unsigned* __restrict__ absmax) {
+  const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi >= ngroups) return;
+  const float scale = absmax ? ldexpf(1.0f, f16_density_exp(absmax)) : 1.0f;
+  const int gpc = ld / 8;
+  const int64_t col = gi / gpc;
+  const int k = int(gi - col * gpc) * 8;
+  const T* src = in + col * ld + k;
+  H* dst = out + col * int64_t(ld) * NB + (k / 32) * NB * 32 + k % 32;
+  typedef H vec8 __attribute__((ext_vector_type(8)));
+  vec8 part[NB];
 #pragma unroll
-  for (int i = 0; i < CNT; ++i) {
-    float x = float(v[i]) * scale;
-    h[i] = H(x);
-    float r = x - float(h[i]);
-    m[i] = H(r);
-    if constexpr (NB == 3) l[i] = H(r - float(m[i]));
+  for (int i = 0; i < 8; ++i) {
+    const float x = float(src[i]) * scale;
+    const H h = H(x);
+    const float r = x - float(h);
+    const H m = H(r);
+    part[0][i] = h;
+    part[1][i] = m;
+    if constexpr (NB == 3) part[2][i] = H(r - float(m));
   }
-  typedef H vec __attribute__((ext_vector_type(CNT)));
-  vec vh, vm, vl;
 #pragma unroll
-  for (int i = 0; i < CNT; ++i) {
-    vh[i] = h[i];
-    vm[i] = m[i];
-    if constexpr (NB == 3) vl[i] = l[i];
-  }
-  *reinterpret_cast<vec*>(dst_h) = vh;
-  if constexpr (NB == 2) {
-    *reinterpret_cast<vec*>(dst_l) = vm;
-  } else {
-    *reinterpret_cast<vec*>(dst_m) = vm;
-    *reinterpret_cast<vec*>(dst_l) = vl;
-  }
+  for (int t = 0; t < NB; ++t) *reinterpret_cast<vec8*>(dst + t * 32) = part[t];
 }
 
 // TAG separates the M2L launches into their own symbols: 1 = M2L, 2 = M2L
@@ -1044,36 +1073,28 @@ __device__ inline void split_store(H* dst_h, H* dst_m, H* dst_l, const T* v, flo
 // One buffer where the registers allow three blocks (32-bit operands, no
 // FP64 sums): measured faster there, as the staging latency is what bounds
 // the split-precision M2L.
-template <int MODE, class TI, int TAG>
+template <int MODE, class TO, int CB, int TAG>
 struct GemmOcc {
-  static constexpr bool THREE = TAG != 2 && MODE != GM_F64 && sizeof(TI) == 4;
+  static constexpr bool THREE = CB == 1 && TAG != 2 && MODE != GM_F64 && sizeof(TO) == 4;
   static constexpr int NBUF = THREE ? 1 : 2;
   static constexpr int MINB = THREE ? 3 : 2;
 };
 
 template <int MODE, class TI, class TO, int CB, int TAG>
-__global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kernel(GemmArgs a) {
+__global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_kernel(GemmArgs a) {
   using Cfg = GemmCfg<MODE, TI, TO, CB>;
   using G = GT<MODE>;
   using TA = typename Cfg::TA;
   using ACC = typename G::acc;
   constexpr int KC = Cfg::KC, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
   constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
-  constexpr int NBUF = GemmOcc<MODE, TI, TAG>::NBUF;
+  constexpr int NBUF = GemmOcc<MODE, TO, CB, TAG>::NBUF;
   __shared__ __align__(16) unsigned char smem[NBUF * Cfg::BUF_BYTES];
   __shared__ int s_ops[kMaxTileSteps];  // the tile's operator indices
-  // FP16 split: exact power-of-two scaling of the densities into range
-  float in_scale = 1.0f, out_scale = 1.0f;
-  if constexpr (MODE == GM_H3) {
-    const float mx = __uint_as_float(*a.absmax);
-    int e = 0;
-    if (mx > 0.0f) {
-      (void)frexpf(mx, &e);  // mx in [2^(e-1), 2^e)
-      e = 14 - e;
-    }
-    in_scale = ldexpf(1.0f, e);
-    out_scale = ldexpf(1.0f, -e - kF16OpExp);
-  }
+  // FP16 split: the densities arrive scaled by 2^e and the operators by
+  // 2^kF16OpExp; the epilogue undoes both (exact powers of two)
+  float out_scale = 1.0f;
+  if constexpr (MODE == GM_H3) out_scale = ldexpf(1.0f, -f16_density_exp(a.absmax) - kF16OpExp);
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   // waves form a 2 x 2 grid: wr picks half of the row blocks, wc half of the
@@ -1132,6 +1153,30 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
     a_goff[j] = rg * ld * NA + t * KC + part * Cfg::EPC;
     a_loff[j] = t * Cfg::A_TSTRIDE + Cfg::off(rl, part);
   }
+  // B staging units of this thread: output slot (column of the tile), part
+  // table and 16-byte chunk.  Split modes use the operators' lane order (the
+  // chunks of a slot, the next slot, the next part, the next slot pair),
+  // which keeps the LDS stores free of bank conflicts.
+  auto b_unit = [&](int u, int& slot, int& t, int& c) __attribute__((always_inline)) {
+    if constexpr (Cfg::SPLIT) {
+      c = u % 4;
+      t = (u / 8) % NB;
+      slot = (u / (8 * NB)) * 2 + ((u / 4) & 1);
+    } else {
+      slot = u / Cfg::B_UNITS_COL;
+      c = u % Cfg::B_UNITS_COL;
+      t = 0;
+    }
+  };
+  int b_loff[Cfg::SPLIT ? Cfg::B_PER_T : 1];
+  if constexpr (Cfg::SPLIT) {
+#pragma unroll
+    for (int j = 0; j < Cfg::B_PER_T; ++j) {
+      int slot, t, c;
+      b_unit(tid + j * 256, slot, t, c);
+      b_loff[j] = t * Cfg::B_TSTRIDE + Cfg::off(slot, c);
+    }
+  }
   // Step bookkeeping of the chunk being loaded: its step, its chunk within
   // the step, and the step's operator and source columns.  The operator
   // index and the source boxes of the following step are fetched a whole
@@ -1150,7 +1195,8 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
     nxt_op = s_ops[sc - sb];
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
-      const int s = (tid + j * 256) / Cfg::B_UNITS_COL;
+      int s, t, c;
+      b_unit(tid + j * 256, s, t, c);
       nxt_src[j] = a.step_src[int64_t(sc) * a.TB + min(s / a.n_rhs, a.TB - 1)];
     }
   };
@@ -1158,10 +1204,13 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
     cur_op = nxt_op;
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
-      const int u = tid + j * 256;
-      const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
+      int s, t, c;
+      b_unit(tid + j * 256, s, t, c);
       const int box = s < ncols ? nxt_src[j] : a.zero_box;
-      b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld + part * (16 / int(sizeof(TI)));
+      if constexpr (Cfg::SPLIT)
+        b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld * NB + t * KC + c * Cfg::EPC;
+      else
+        b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld + c * (16 / int(sizeof(TI)));
     }
   };
   auto load_regs = [&](auto P) __attribute__((always_inline)) {
@@ -1170,7 +1219,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
     const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + NA * k0;
 #pragma unroll
     for (int j = 0; j < Cfg::A_PER_T; ++j) ra[R][j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
-    const TI* inb = static_cast<const TI*>(a.in) + k0;
+    const TI* inb = static_cast<const TI*>(a.in) + (Cfg::SPLIT ? NB * k0 : k0);
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) rb[R][j] = *reinterpret_cast<const u32x4*>(inb + b_goff[j]);
   };
@@ -1189,11 +1238,14 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
     TA* Bs = As + Cfg::A_ELEMS;
 #pragma unroll
     for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[R][j];
-    constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
+    if constexpr (Cfg::SPLIT) {
 #pragma unroll
-    for (int j = 0; j < Cfg::B_PER_T; ++j) {
-      const int u = tid + j * 256;
-      {
+      for (int j = 0; j < Cfg::B_PER_T; ++j) *reinterpret_cast<u32x4*>(Bs + b_loff[j]) = rb[R][j];
+    } else {
+      constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
+#pragma unroll
+      for (int j = 0; j < Cfg::B_PER_T; ++j) {
+        const int u = tid + j * 256;
         const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
         const TI* vals = reinterpret_cast<const TI*>(&rb[R][j]);
         // input unit `part` holds k = part*EPU .. part*EPU + EPU - 1
@@ -1202,26 +1254,16 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TI, TAG>::MINB)) void gemm_kern
           // one or more whole LDS chunks
 #pragma unroll
           for (int q = 0; q < EPU / EPC; ++q) {
-            const int chunk = part * (EPU / EPC) + q;
-            if constexpr (BF) {
-              TA* h = Bs + Cfg::off(s, chunk);
-              split_store<TA, NB, TI, EPC>(h, h + Cfg::B_TSTRIDE, h + (NB - 1) * Cfg::B_TSTRIDE, vals + q * EPC, in_scale);
-            } else {
-              TA* d = Bs + Cfg::off(s, chunk);
+            TA* d = Bs + Cfg::off(s, part * (EPU / EPC) + q);
 #pragma unroll
-              for (int x = 0; x < EPC; ++x) d[x] = TA(vals[q * EPC + x]);
-            }
+            for (int x = 0; x < EPC; ++x) d[x] = TA(vals[q * EPC + x]);
           }
         } else {
           // part of one LDS chunk
           const int k0 = part * EPU;
           TA* d = Bs + Cfg::off(s, k0 / EPC) + k0 % EPC;
-          if constexpr (BF) {
-            split_store<TA, NB, TI, EPU>(d, d + Cfg::B_TSTRIDE, d + (NB - 1) * Cfg::B_TSTRIDE, vals, in_scale);
-          } else {
 #pragma unroll
-            for (int x = 0; x < EPU; ++x) d[x] = TA(vals[x]);
-          }
+          for (int x = 0; x < EPU; ++x) d[x] = TA(vals[x]);
         }
       }
     }
@@ -1476,6 +1518,11 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64,
   }
 }
 
+// Where the near field forks off the evaluation stream: 0 right after the
+// gather (it overlaps P2M..M2L), 1 just before M2L (it overlaps M2L only).
+static int g_near_fork = 0;
+void set_near_fork(int v) { g_near_fork = v; }
+
 // Per-device auxiliary stream and fork/join events of the pipeline (default
 // priority, non-blocking; created once and kept for the process).
 struct Aux {
@@ -1546,22 +1593,26 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.dn_eq = dn_eq;
   base.pot = W.pot;
   base.ntgt = F.ntgt;
-  {
-    // fork: the near field needs only the gathered charges; it runs on the
-    // auxiliary stream while the multipole passes run on s
+  // The near field needs only the gathered charges; it runs on the
+  // auxiliary stream, forked either here or just before M2L (g_near_fork),
+  // and is joined before the far field.
+  auto fork_near = [&]() {
     HIPCHECK(hipEventRecord(aux.forked, s));
     HIPCHECK(hipStreamWaitEvent(aux.stream, aux.forked, 0));
     const hipStream_t ns = g_prof.on ? s : aux.stream;
-    PhaseScope ps(PH_NEAR, ns);
-    P2PArgs<T> a = base;
-    a.work = F.leaf_boxes;
-    a.l1_off = F.u_off;
-    a.l1_items = F.u_items;
-    a.l2_off = F.w_off;
-    a.l2_items = F.w_items;
-    run_p2p_rc<T, MODE_NEAR, 32>(a, F.n_leaf, n_rhs, false, ns, ps);
-  }
-  HIPCHECK(hipEventRecord(aux.joined, aux.stream));
+    {
+      PhaseScope ps(PH_NEAR, ns);
+      P2PArgs<T> a = base;
+      a.work = F.leaf_boxes;
+      a.l1_off = F.u_off;
+      a.l1_items = F.u_items;
+      a.l2_off = F.w_off;
+      a.l2_items = F.w_items;
+      run_p2p_rc<T, MODE_NEAR, 32>(a, F.n_leaf, n_rhs, false, ns, ps);
+    }
+    HIPCHECK(hipEventRecord(aux.joined, aux.stream));
+  };
+  if (g_near_fork == 0) fork_near();
   {
     PhaseScope ps(PH_P2M, s);
     P2PArgs<T> a = base;
@@ -1591,6 +1642,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, 0, ld, F.nbox, n_rhs, up_chk, up_eq, false, s, ps);
     }
   }
+  if (g_near_fork == 1) fork_near();
   {
     // operand of M2L: upward densities, or (check form) upward check potentials
     const T* m2l_in = check_form ? up_chk : up_eq;
@@ -1616,30 +1668,52 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       LAUNCHCHECK("absmax_kernel");
       ps.launches += 2;
     };
-    if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) scale16();
+    const bool f16 = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3;
+    if (f16) scale16();
+    // split modes: the operand is split into its 16-bit parts once
+    auto split_in = [&](auto mode_tag, const T* in, const unsigned* amax) {
+      constexpr int MODE = decltype(mode_tag)::value;
+      using H = typename GT<MODE>::TA;
+      PhaseScope pp(PH_M2L_PREP, s);
+      const int64_t ngroups = int64_t(F.nbox + 1) * n_rhs * ld / 8;
+      if (int64_t(sizeof(H)) * GT<MODE>::NB * ngroups * 8 > int64_t(W.split_bytes))
+        raise(KIFMM_EINVAL, "evaluate: split operand buffer too small");
+      hipLaunchKernelGGL((split_kernel<T, H, GT<MODE>::NB>), dim3(unsigned((ngroups + 255) / 256)), dim3(256), 0,
+                         s, in, static_cast<H*>(W.split), ngroups, ld, amax);
+      LAUNCHCHECK("split_kernel");
+      pp.launches++;
+    };
+    if (f16) split_in(std::integral_constant<int, GM_H3>(), m2l_in, W.absmax);
+    if constexpr (sizeof(T) == 4) {
+      if (prec == KIFMM_M2L_BF16X3) split_in(std::integral_constant<int, GM_BF3>(), up_eq, nullptr);
+      if (prec == KIFMM_M2L_BF16X5) split_in(std::integral_constant<int, GM_BF5>(), up_eq, nullptr);
+    }
     PhaseScope ps(PH_M2L, s);
     const bool fp64_sum = O.p >= g_m2l_fp64_sum_min_p;
-    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const T* in, const unsigned* amax) {
+    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const unsigned* amax) {
       constexpr int MODE = decltype(mode_tag)::value;
-      constexpr int64_t parts = (MODE == GM_F32 || MODE == GM_F64) ? 1 : 2;
+      constexpr bool split = !(MODE == GM_F32 || MODE == GM_F64);
+      using TIn = typename std::conditional<split, typename GT<MODE>::TA, T>::type;
+      const TIn* in = split ? static_cast<const TIn*>(W.split) : reinterpret_cast<const TIn*>(m2l_in);
+      constexpr int64_t parts = split ? 2 : 1;
       if (fp64_sum)
-        run_gemm<MODE, T, T, 2>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
+        run_gemm<MODE, TIn, T, 2>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
       else
-        run_gemm<MODE, T, T, 1>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
+        run_gemm<MODE, TIn, T, 1>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
     };
     const void* op32 = check_form ? static_cast<const void*>(O.m2lc32) : static_cast<const void*>(O.m2l32);
     const void* oph = check_form ? O.m2lc_h : O.m2l_h;
     if (prec == KIFMM_FP64) {
       run_gemm<GM_F64, T, T, 1>(F.m2l, O.m2l64, nn, ld, F.nbox, n_rhs, m2l_in, dn_chk, true, s, ps);
     } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
-      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, m2l_in, nullptr);
-    } else if (prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3) {
-      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, m2l_in, W.absmax);
+      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, nullptr);
+    } else if (f16) {
+      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, W.absmax);
     } else if constexpr (sizeof(T) == 4) {
       if (prec == KIFMM_M2L_BF16X3)
-        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_b, up_eq, nullptr);
+        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_b, nullptr);
       else
-        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, up_eq, nullptr);
+        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, nullptr);
     }
   }
   {
@@ -1717,6 +1791,7 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
   DevWork* W = work_for(F, fp64, n_rhs);
+  if (need.bf16 || need.f16) ensure_split(F, W);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto launch_all = [&]() {
     if (fp64) {
@@ -1737,7 +1812,8 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
                                   reinterpret_cast<const void*>(intptr_t(io_fp64)), s, O, W,
                                   reinterpret_cast<const void*>(intptr_t(g_far_fp64_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_check_min_p)),
-                                  reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p))};
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p)),
+                                  reinterpret_cast<const void*>(intptr_t(g_near_fork))};
   for (int k = 0; k < F.nprob; ++k) {
     key.push_back(charges[k]);
     key.push_back(potentials[k]);
