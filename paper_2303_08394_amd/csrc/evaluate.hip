@@ -485,6 +485,9 @@ template <> struct V4<double> { using type = double4; };
 
 __device__ inline float rinv(float r2) { return r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f; }
 __device__ inline double rinv(double r2) { return r2 > 0.0 ? rsqrt(r2) : 0.0; }
+// for pairs that cannot coincide (r2 > 0)
+__device__ inline float rinv_nonzero(float r2) { return __builtin_amdgcn_rsqf(r2); }
+__device__ inline double rinv_nonzero(double r2) { return rsqrt(r2); }
 
 constexpr int kMaxProb = 64;
 struct PtrPack {
@@ -632,7 +635,8 @@ struct P2PArgs {
 template <class T, int RC>
 struct P2PCfg {
   static constexpr int NT = 256;
-  static constexpr int PB = int(sizeof(typename V4<T>::type)) + RC * int(sizeof(T));
+  // staged source: position (+ the charge in w when RC == 1), charges of RC > 1 columns
+  static constexpr int PB = int(sizeof(typename V4<T>::type)) + (RC > 1 ? RC * int(sizeof(T)) : 0);
   // The batch size depends on T only, so every right-hand side sees the same
   // summation order whatever RC is (multi-RHS columns equal single runs bitwise).
   static constexpr int CAP = sizeof(T) == 4 ? 1024 : 512;
@@ -650,13 +654,14 @@ __device__ inline double4 frame(int4 a, int4 b) {
   return g;
 }
 
-constexpr int kMaxSeg = 256, kNch = 4;
+constexpr int kMaxSeg = 160, kNch = 4;  // segment window (any count is processed in windows)
 
 struct SegTable {
   int pre[kMaxSeg + 1];
   int id[kMaxSeg];
   int kind[kMaxSeg];
   double4 geo[kMaxSeg];
+  int self_k;  // index of the target box's own particle segment, or -1
 };
 
 // Source segment si of work item wi (target box B) for the given mode.
@@ -714,6 +719,11 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
   for (int sw = s0; sw < s1; sw += kMaxSeg) {
     const int nw = min(kMaxSeg, s1 - sw);
     __syncthreads();
+    if (tid == 0) {
+      st.pre[0] = 0;
+      st.self_k = -1;
+    }
+    __syncthreads();
     if (tid < nw) {
       int kind, id, size;
       double4 g;
@@ -722,8 +732,10 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
       st.id[tid] = id;
       st.geo[tid] = g;
       st.pre[tid + 1] = size;
+      // the target box's own particles (the one segment whose sources can
+      // coincide with targets: equal points always share a leaf)
+      if (kind == SEG_POINTS && size > 0 && id == a.box_src[B].x) st.self_k = tid;
     }
-    if (tid == 0) st.pre[0] = 0;
     __syncthreads();
     for (int off = 1; off < nw; off <<= 1) {
       int v = (tid < nw && tid >= off) ? st.pre[tid + 1 - off] : 0;
@@ -746,6 +758,7 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
         const int kind = st.kind[lo];
         const double4 g = st.geo[lo];
         double px, py, pz;
+        U q0 = U(0);  // first right-hand side (staged with the position when RC == 1)
         if (kind == SEG_POINTS) {
           const int64_t pi = int64_t(st.id[lo]) + local;
           double4 p = a.src64[pi];
@@ -755,7 +768,9 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 #pragma unroll
           for (int r = 0; r < RC; ++r) {
             int rr = rhs0 + r;
-            s_q[r * CAP + j] = rr < a.n_rhs ? U(a.qs[int64_t(rr) * a.nsrc + pi]) : U(0);
+            const U qv = rr < a.n_rhs ? U(a.qs[int64_t(rr) * a.nsrc + pi]) : U(0);
+            if (r == 0) q0 = qv;
+            if constexpr (RC > 1) s_q[r * CAP + j] = qv;
           }
         } else {
           double4 s = a.surf[local];
@@ -767,14 +782,16 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 #pragma unroll
           for (int r = 0; r < RC; ++r) {
             int rr = rhs0 + r;
-            s_q[r * CAP + j] = rr < a.n_rhs ? U(dens[(col0 + rr) * a.ld + local]) : U(0);
+            const U qv = rr < a.n_rhs ? U(dens[(col0 + rr) * a.ld + local]) : U(0);
+            if (r == 0) q0 = qv;
+            if constexpr (RC > 1) s_q[r * CAP + j] = qv;
           }
         }
         V v;
         v.x = U(px);
         v.y = U(py);
         v.z = U(pz);
-        v.w = U(0);
+        v.w = q0;  // one right-hand side: the charge rides along with the position
         s_pos[j] = v;
       }
       __syncthreads();
@@ -785,12 +802,48 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 #pragma unroll
           for (int r = 0; r < RC; ++r) part[r] = U(0);
           const U x = ux[c], y = uy[c], z = uz[c];
-          for (int j = sl; j < nb; j += SL) {
-            V s = s_pos[j];
-            U dx = x - s.x, dy = y - s.y, dz = z - s.z;
-            U ri = rinv(dx * dx + dy * dy + dz * dz);
+          // sources j = sl, sl + SL, ... in order; four per trip so that their
+          // LDS reads are in flight together (same summation order)
+          auto pair = [&](const V& s, int j, auto checked) __attribute__((always_inline)) {
+            const U dx = x - s.x, dy = y - s.y, dz = z - s.z;
+            const U r2 = dx * dx + dy * dy + dz * dz;
+            U ri;
+            if constexpr (decltype(checked)::value) ri = rinv(r2);   // coincident pair -> 0
+            else ri = rinv_nonzero(r2);
+            if constexpr (RC == 1) {
+              part[0] += s.w * ri;
+            } else {
 #pragma unroll
-            for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
+              for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
+            }
+          };
+          // staged sources [j, end) with stride SL, in order
+          auto run = [&](int j, int end, auto checked) __attribute__((always_inline)) {
+            for (; j + 3 * SL < end; j += 4 * SL) {
+              const V s0 = s_pos[j], s1 = s_pos[j + SL], s2 = s_pos[j + 2 * SL], s3 = s_pos[j + 3 * SL];
+              pair(s0, j, checked);
+              pair(s1, j + SL, checked);
+              pair(s2, j + 2 * SL, checked);
+              pair(s3, j + 3 * SL, checked);
+            }
+            for (; j < end; j += SL) pair(s_pos[j], j, checked);
+            return j;
+          };
+          const std::true_type chk;
+          const std::false_type nochk;
+          if constexpr (MODE == MODE_LEAF || MODE == MODE_NEAR) {
+            // only the target box's own particles need the coincidence test;
+            // the three ranges keep the order j = sl, sl + SL, ...
+            int lo = nb, hi = nb;
+            if (st.self_k >= 0) {
+              lo = min(max(st.pre[st.self_k] - b0, 0), nb);
+              hi = min(max(st.pre[st.self_k + 1] - b0, 0), nb);
+            }
+            int j = run(sl, lo, nochk);
+            j = run(j, hi, chk);
+            run(j, nb, nochk);
+          } else {
+            run(sl, nb, chk);
           }
 #pragma unroll
           for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
