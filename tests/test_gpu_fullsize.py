@@ -67,6 +67,10 @@ def check_single(prob, precision, tol, n_sample):
 
 
 def test_uniform_1m_fullsize():
+    check_single(I.uniform_1m(), "bf16x3", 1e-5, 100)
+
+
+def test_uniform_1m_fullsize_f16x3():
     check_single(I.uniform_1m(), "f16x3", 1e-5, 100)
 
 
