@@ -302,7 +302,8 @@ void kifmm_ops_destroy(kifmm_ops* ops) {
 kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
   if (!key) return fail(KIFMM_EINVAL, "set_tuning: null key");
   if (std::strcmp(key, "m2l_tile_cols") == 0) {
-    if (value != 64 && value != 128) return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64 or 128");
+    if (value != 64 && value != 128 && value != 192)
+      return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64, 128 or 192");
     g_m2l_tile_cols = value;
     return KIFMM_OK;
   }
@@ -312,7 +313,7 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
     return KIFMM_OK;
   }
   if (std::strcmp(key, "near_fork") == 0) {
-    if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: near_fork must be 0 or 1");
+    if (value < 0 || value > 2) return fail(KIFMM_EINVAL, "set_tuning: near_fork must be 0, 1 or 2");
     set_near_fork(value);
     return KIFMM_OK;
   }

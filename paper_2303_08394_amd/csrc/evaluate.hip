@@ -732,9 +732,16 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
       st.id[tid] = id;
       st.geo[tid] = g;
       st.pre[tid + 1] = size;
-      // the target box's own particles (the one segment whose sources can
-      // coincide with targets: equal points always share a leaf)
-      if (kind == SEG_POINTS && size > 0 && id == a.box_src[B].x) st.self_k = tid;
+      // the segment whose coincidence test differs from the others': near
+      // field, the target box's own particles (the only sources that can
+      // coincide with targets: equal points always share a leaf); far field,
+      // the box's own downward equivalent surface (at 2.95 r, never within
+      // 1.95 r of its particles)
+      if constexpr (MODE == MODE_LEAF || MODE == MODE_NEAR) {
+        if (kind == SEG_POINTS && size > 0 && id == a.box_src[B].x) st.self_k = tid;
+      } else if constexpr (MODE == MODE_FAR) {
+        if (kind == SEG_DN_EQUIV && size > 0) st.self_k = tid;
+      }
     }
     __syncthreads();
     for (int off = 1; off < nw; off <<= 1) {
@@ -831,17 +838,25 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
           };
           const std::true_type chk;
           const std::false_type nochk;
+          // the ranges keep the order j = sl, sl + SL, ...
+          int lo = nb, hi = nb;
+          if (st.self_k >= 0) {
+            lo = min(max(st.pre[st.self_k] - b0, 0), nb);
+            hi = min(max(st.pre[st.self_k + 1] - b0, 0), nb);
+          }
           if constexpr (MODE == MODE_LEAF || MODE == MODE_NEAR) {
-            // only the target box's own particles need the coincidence test;
-            // the three ranges keep the order j = sl, sl + SL, ...
-            int lo = nb, hi = nb;
-            if (st.self_k >= 0) {
-              lo = min(max(st.pre[st.self_k] - b0, 0), nb);
-              hi = min(max(st.pre[st.self_k + 1] - b0, 0), nb);
-            }
+            // only the target box's own particles need the coincidence test
             int j = run(sl, lo, nochk);
             j = run(j, hi, chk);
             run(j, nb, nochk);
+          } else if constexpr (MODE == MODE_FAR) {
+            // all but the box's own downward surface need it
+            int j = run(sl, lo, chk);
+            j = run(j, hi, nochk);
+            run(j, nb, chk);
+          } else if constexpr (MODE == MODE_P2M) {
+            // check surface at 2.95 r, sources inside the box: never coincide
+            run(sl, nb, nochk);
           } else {
             run(sl, nb, chk);
           }
@@ -1045,31 +1060,36 @@ struct GemmArgs {
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
+constexpr int kFewTiles = 128;  // below this, non-M2L plans use 32-row blocks
 constexpr int kMaxTileSteps = 320;  // >= 316, the M2L offsets a tile can hold
 
-template <int MODE, class TI, class TO, int CB>
+template <int MODE, class TI, class TO, int CB, int CG = 1, int RB = kRB>
 struct GemmCfg {
   using G = GT<MODE>;
   using TA = typename G::TA;
-  static constexpr int KC = G::KC, NB = G::NB, TC = 64 * CB;
+  // RB row blocks of 16 per block (kRB = 10: all 160 rows; 2: 32-row groups,
+  // five blocks per tile, for plans with few tiles)
+  static constexpr int ROWS = RB * 16;
+  // CG column groups of 4 waves: NT threads, TC output columns per block
+  static constexpr int KC = G::KC, NB = G::NB, TC = 64 * CB * CG, NT = 256 * CG;
   static constexpr int NA = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3) ? 2 : 1;  // operator tables
   // per buffer: NA operator tiles [ROWS][KC] and NB column tiles [TC][KC] of TA
   // operator part tables sit A_TSTRIDE elements apart: 128 bytes more than a
   // multiple of 256, so the two parts of one row land in different banks
-  static constexpr int A_TSTRIDE = kROWS * KC + (NA > 1 ? 128 / int(sizeof(TA)) : 0);
+  static constexpr int A_TSTRIDE = ROWS * KC + (NA > 1 ? 128 / int(sizeof(TA)) : 0);
   static constexpr int B_TSTRIDE = TC * KC + (NB > 1 ? 128 / int(sizeof(TA)) : 0);  // likewise
   static constexpr int A_ELEMS = NA * A_TSTRIDE, B_ELEMS = NB * B_TSTRIDE;
   static constexpr int BUF_BYTES = (A_ELEMS + B_ELEMS) * int(sizeof(TA));
   // 16-byte global units per chunk
   static constexpr int A_UNITS_ROW = KC * int(sizeof(TA)) / 16;         // per table row
-  static constexpr int A_UNITS = NA * kROWS * A_UNITS_ROW;
-  static constexpr int A_PER_T = (A_UNITS + 255) / 256;
+  static constexpr int A_UNITS = NA * ROWS * A_UNITS_ROW;
+  static constexpr int A_PER_T = (A_UNITS + NT - 1) / NT;  // units past A_UNITS repeat earlier ones
   // split modes read densities already split into NB 16-bit parts,
   // chunk-interleaved like the operators ([column][ld / KC][NB][KC])
   static constexpr bool SPLIT = NA > 1;
   static constexpr int B_UNITS_COL = SPLIT ? NB * KC * int(sizeof(TA)) / 16 : KC * int(sizeof(TI)) / 16;
   static constexpr int B_UNITS = TC * B_UNITS_COL;
-  static constexpr int B_PER_T = (B_UNITS + 255) / 256;
+  static constexpr int B_PER_T = (B_UNITS + NT - 1) / NT;
   // LDS rows are KC elements with no padding; the 16-byte chunks of a row are
   // XOR-swizzled so that one chunk column of consecutive rows (a fragment
   // read: lane = row) and the staging stores avoid bank conflicts.  Both
@@ -1093,13 +1113,17 @@ struct GemmCfg {
 // converts 8 consecutive elements of a column (a 16-byte chunk per part).
 template <class T, class H, int NB>
 __global__ void split_kernel(const T* __restrict__ in, H* __restrict__ out, int64_t ngroups, int ld,
-                             const unsigned* __restrict__ absmax) {
+                             const unsigned* __restrict__ absmax, T* __restrict__ zero_out) {
   const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (gi >= ngroups) return;
   const float scale = absmax ? ldexpf(1.0f, f16_density_exp(absmax)) : 1.0f;
   const int gpc = ld / 8;
   const int64_t col = gi / gpc;
   const int k = int(gi - col * gpc) * 8;
+  // the same elements of the M2L output (the downward check potentials),
+  // which the split M2L adds into, start at zero
+#pragma unroll
+  for (int i = 0; i < 8; ++i) zero_out[col * ld + k + i] = T(0);
   const T* src = in + col * ld + k;
   H* dst = out + col * int64_t(ld) * NB + (k / 32) * NB * 32 + k % 32;
   typedef H vec8 __attribute__((ext_vector_type(8)));
@@ -1126,22 +1150,28 @@ __global__ void split_kernel(const T* __restrict__ in, H* __restrict__ out, int6
 // One buffer where the registers allow three blocks (32-bit operands, no
 // FP64 sums): measured faster there, as the staging latency is what bounds
 // the split-precision M2L.
-template <int MODE, class TO, int CB, int TAG>
+template <int MODE, class TO, int CB, int TAG, int CG = 1>
 struct GemmOcc {
-  static constexpr bool THREE = CB == 1 && TAG != 2 && MODE != GM_F64 && sizeof(TO) == 4;
+  // blocks of CG > 1 column groups (3 x 4 waves, one block per CU) share one
+  // operator staging among 192 columns; only for 32-bit outputs, no FP64 sums
+  static constexpr bool WIDE_OK = CB == 1 && TAG != 2 && MODE != GM_F64 && sizeof(TO) == 4;
+  static constexpr bool THREE = CG == 1 && WIDE_OK;
   static constexpr int NBUF = THREE ? 1 : 2;
-  static constexpr int MINB = THREE ? 3 : 2;
+  static constexpr int MINB = CG > 1 ? 1 : (THREE ? 3 : 2);
 };
 
-template <int MODE, class TI, class TO, int CB, int TAG>
-__global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_kernel(GemmArgs a) {
-  using Cfg = GemmCfg<MODE, TI, TO, CB>;
+template <int MODE, class TI, class TO, int CB, int TAG, int CG = 1, int RB = kRB>
+__global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) void gemm_kernel(GemmArgs a) {
+  using Cfg = GemmCfg<MODE, TI, TO, CB, CG, RB>;
+  static_assert(RB % 2 == 0, "row blocks are split between two waves");
+  constexpr int NT = Cfg::NT;
   using G = GT<MODE>;
   using TA = typename Cfg::TA;
   using ACC = typename G::acc;
   constexpr int KC = Cfg::KC, NB = Cfg::NB, TC = Cfg::TC, NA = Cfg::NA;
   constexpr bool BF = (MODE == GM_BF3 || MODE == GM_BF5 || MODE == GM_H3);  // split modes
-  constexpr int NBUF = GemmOcc<MODE, TO, CB, TAG>::NBUF;
+  constexpr int NBUF = GemmOcc<MODE, TO, CB, TAG, CG>::NBUF;
+  static_assert(CG == 1 || GemmOcc<MODE, TO, CB, TAG, CG>::WIDE_OK, "wide blocks need 32-bit outputs");
   __shared__ __align__(16) unsigned char smem[NBUF * Cfg::BUF_BYTES];
   __shared__ int s_ops[kMaxTileSteps];  // the tile's operator indices
   // FP16 split: the densities arrive scaled by 2^e and the operators by
@@ -1152,11 +1182,15 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   // waves form a 2 x 2 grid: wr picks half of the row blocks, wc half of the
   // column blocks, so each operator fragment is read by two waves, not four
-  constexpr int RBW = kRB / 2, CBW = 2 * CB;
-  const int wr = wave >> 1, wc = wave & 1;
+  constexpr int RBW = RB / 2, CBW = 2 * CB;
+  const int wr = (wave & 3) >> 1, wc = wave & 1;
+  // first column of this wave's column group; a plan wider than the block
+  // is covered by blockIdx.z slices of TC columns
+  const int col0 = blockIdx.z * TC;
+  const int cbase = col0 + (wave >> 2) * 64 * CB;
   const int tile = blockIdx.x;
-  const int row0 = blockIdx.y * kROWS;
-  const int nrb = min(kRB, (a.ld - row0) / 16);
+  const int row0 = blockIdx.y * Cfg::ROWS;
+  const int nrb = min(RB, (a.ld - row0) / 16);
   const int ld = a.ld;
   const int ncols = a.TB * a.n_rhs;
   const int sb = a.step_beg[tile], se = a.step_beg[tile + 1];
@@ -1192,14 +1226,14 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
   // (row, part, split part) and the LDS slots they land in.  Operator rows
   // past ld are clamped to a valid row: they only feed output rows that the
   // epilogue discards.
-  static_assert(Cfg::A_UNITS % 256 == 0 && Cfg::B_UNITS % 256 == 0, "staging units per thread");
+  static_assert(Cfg::B_UNITS % NT == 0, "staging units per thread");
   static_assert(NA == 1 || KC == 32, "split operator tables are interleaved in blocks of 32");
   int a_goff[Cfg::A_PER_T], a_loff[Cfg::A_PER_T];
 #pragma unroll
   for (int j = 0; j < Cfg::A_PER_T; ++j) {
     // consecutive lanes: the chunks of a row, then the next row, then the
     // next part table, then the next pair of rows
-    const int u = tid + j * 256;
+    const int u = (tid + j * NT) % Cfg::A_UNITS;
     const int part = u % Cfg::CPR, rsub = (u / Cfg::CPR) & 1, t = (u / (2 * Cfg::CPR)) % NA;
     const int rl = (u / (2 * Cfg::CPR * NA)) * 2 + rsub;
     const int rg = min(row0 + rl, ld - 1);
@@ -1226,7 +1260,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
       int slot, t, c;
-      b_unit(tid + j * 256, slot, t, c);
+      b_unit(tid + j * NT, slot, t, c);
       b_loff[j] = t * Cfg::B_TSTRIDE + Cfg::off(slot, c);
     }
   }
@@ -1249,7 +1283,8 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
       int s, t, c;
-      b_unit(tid + j * 256, s, t, c);
+      b_unit(tid + j * NT, s, t, c);
+      s += col0;
       nxt_src[j] = a.step_src[int64_t(sc) * a.TB + min(s / a.n_rhs, a.TB - 1)];
     }
   };
@@ -1258,7 +1293,8 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
 #pragma unroll
     for (int j = 0; j < Cfg::B_PER_T; ++j) {
       int s, t, c;
-      b_unit(tid + j * 256, s, t, c);
+      b_unit(tid + j * NT, s, t, c);
+      s += col0;
       const int box = s < ncols ? nxt_src[j] : a.zero_box;
       if constexpr (Cfg::SPLIT)
         b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld * NB + t * KC + c * Cfg::EPC;
@@ -1298,7 +1334,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
       constexpr int EPU = 16 / int(sizeof(TI));  // input elements per unit
 #pragma unroll
       for (int j = 0; j < Cfg::B_PER_T; ++j) {
-        const int u = tid + j * 256;
+        const int u = tid + j * NT;
         const int s = u / Cfg::B_UNITS_COL, part = u % Cfg::B_UNITS_COL;
         const TI* vals = reinterpret_cast<const TI*>(&rb[R][j]);
         // input unit `part` holds k = part*EPU .. part*EPU + EPU - 1
@@ -1334,7 +1370,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
       TA bv[CBW][KL], av[RBW][KL];
 #pragma unroll
       for (int c = 0; c < CBW; ++c) {
-        const int col = wc * 16 * CBW + c * 16 + r16;
+        const int col = cbase - col0 + wc * 16 * CBW + c * 16 + r16;
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
           const TA* p = Bs + Cfg::off(col, g * NCH + q);
@@ -1374,7 +1410,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
       vec8 bh[CBW], bm[CBW], bl[CBW];
 #pragma unroll
       for (int c = 0; c < CBW; ++c) {
-        const int col = wc * 16 * CBW + c * 16 + r16;
+        const int col = cbase - col0 + wc * 16 * CBW + c * 16 + r16;
         const int o = Cfg::off(col, g);
         bh[c] = *reinterpret_cast<const vec8*>(Bs + o);
         bl[c] = *reinterpret_cast<const vec8*>(Bs + (NB - 1) * Cfg::B_TSTRIDE + o);
@@ -1417,7 +1453,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
   };
 
   if (nchunks > 0) {
-    for (int i = tid; i < se - sb; i += 256) s_ops[i] = a.step_op[sb + i];
+    for (int i = tid; i < se - sb; i += NT) s_ops[i] = a.step_op[sb + i];
     __syncthreads();
     fetch_step(sb);
     begin_step();
@@ -1485,7 +1521,7 @@ __global__ __launch_bounds__(256, (GemmOcc<MODE, TO, CB, TAG>::MINB)) void gemm_
 
 #pragma unroll
   for (int c = 0; c < CBW; ++c) {
-    const int s = wc * 16 * CBW + c * 16 + r16;
+    const int s = cbase + wc * 16 * CBW + c * 16 + r16;
     if (s < ncols) {
       const int b = s / a.n_rhs, r = s % a.n_rhs;
       const int box = a.tile_cols[int64_t(tile) * a.TB + b];
@@ -1529,16 +1565,35 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
                      PhaseScope& ps, const unsigned* absmax = nullptr) {
   if (P.ntile == 0) return;
   const int ncols = P.TB * n_rhs;
-  if (ncols > 128) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
+  if (ncols > 192) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
   if (P.max_tile_steps > kMaxTileSteps) raise(KIFMM_EUNSUPPORTED, "GEMM tile with too many operator steps");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
-  if (ncols > 64)
+  // plans with few tiles (the coarse levels of M2M, L2L and the solves) run
+  // 32-row blocks: five times the blocks, a fifth of the work per block
+  if constexpr (TAG == 0) {
+    if (P.ntile < kFewTiles && ncols <= 64) {
+      grid.y = (ld + 31) / 32;
+      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 1, 2>), grid, dim3(256), 0, s, g);
+      LAUNCHCHECK("gemm_kernel");
+      ps.launches++;
+      return;
+    }
+  }
+  if (ncols > 128) {
+    if constexpr (GemmOcc<MODE, TO, 1, TAG, 3>::WIDE_OK) {
+      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 3>), grid, dim3(768), 0, s, g);
+    } else {
+      grid.z = (ncols + 63) / 64;  // 64-column slices of the wide tiles
+      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG>), grid, dim3(256), 0, s, g);
+    }
+  } else if (ncols > 64) {
     hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG>), grid, dim3(256), 0, s, g);
-  else
+  } else {
     hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG>), grid, dim3(256), 0, s, g);
+  }
   LAUNCHCHECK("gemm_kernel");
   ps.launches++;
 }
@@ -1572,7 +1627,8 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64,
 }
 
 // Where the near field forks off the evaluation stream: 0 right after the
-// gather (it overlaps P2M..M2L), 1 just before M2L (it overlaps M2L only).
+// gather, 2 after P2M (it then overlaps the latency-bound M2M / C2E chain
+// rather than P2M), 1 just before M2L.
 static int g_near_fork = 0;
 void set_near_fork(int v) { g_near_fork = v; }
 
@@ -1673,6 +1729,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.out_col = up_chk;
     run_p2p_rc<T, MODE_P2M, 64>(a, F.n_p2m, n_rhs, false, s, ps);
   }
+  if (g_near_fork == 2) fork_near();
   for (int l = F.depth; l >= 2; --l) {
     {
       PhaseScope ps(PH_M2M, s);
@@ -1699,9 +1756,12 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   {
     // operand of M2L: upward densities, or (check form) upward check potentials
     const T* m2l_in = check_form ? up_chk : up_eq;
-    {
+    const bool split_mode = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3 ||
+                            prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5;
+    if (!split_mode) {
       // M2L adds its tiles into zeroed downward check potentials with
-      // atomics (two terms at most per value); P2L and L2L add afterwards
+      // atomics (two terms at most per value); P2L and L2L add afterwards.
+      // (The split pass of the split modes zeroes them itself.)
       PhaseScope ps(PH_M2L_PREP, s);
       int64_t n16 = int64_t(W.col_bytes / 16);
       hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, static_cast<uint4*>(W.dn_chk), n16);
@@ -1732,7 +1792,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       if (int64_t(sizeof(H)) * GT<MODE>::NB * ngroups * 8 > int64_t(W.split_bytes))
         raise(KIFMM_EINVAL, "evaluate: split operand buffer too small");
       hipLaunchKernelGGL((split_kernel<T, H, GT<MODE>::NB>), dim3(unsigned((ngroups + 255) / 256)), dim3(256), 0,
-                         s, in, static_cast<H*>(W.split), ngroups, ld, amax);
+                         s, in, static_cast<H*>(W.split), ngroups, ld, amax, dn_chk);
       LAUNCHCHECK("split_kernel");
       pp.launches++;
     };

@@ -225,3 +225,22 @@ def test_batch_graph_replays_match_eager():
             s.synchronize()
             for o, w in zip(outs, eager):
                 np.testing.assert_array_equal(o.cpu().numpy(), w)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp32"])
+def test_wide_m2l_tiles_equal_narrow(precision):
+    """192-column M2L tiles (768-thread blocks) give the same values, bitwise,
+    as 64-column tiles: every box's M2L is the sum of its two parity parts,
+    each accumulated over its offsets in the same order whatever the tile."""
+    name = "sphere12k_nc32_p6"
+    x, q, tgt, p, kw = _case(name)
+    tree = K.Tree(x, tgt, **kw)
+    narrow = gpu_eval(tree, p, q, precision)
+    K.set_tuning("m2l_tile_cols", 192)
+    try:
+        wide = gpu_eval(tree, p, q, precision)  # the plans are rebuilt for the new width
+    finally:
+        K.set_tuning("m2l_tile_cols", 64)
+    np.testing.assert_array_equal(wide, narrow)
+    want = oracle(name, x, q, tgt, p, **kw)
+    assert rel(wide, want) < TOL32
