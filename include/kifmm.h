@@ -197,8 +197,11 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
 
 /* Process-wide tuning knobs of the evaluation kernels (a change of a plan
  * knob rebuilds the plans at the next evaluate).
- *   "m2l_tile_cols":  output columns (box x right-hand side) per M2L block,
- *                     64 (default) or 128.
+ *   "m2l_tile_cols":  output columns (box x right-hand side) per M2L tile,
+ *                     64 (default), 128 or 192.  With 192, M2L kernels with
+ *                     32-bit outputs run one 768-thread block per tile; the
+ *                     others cover the tile with 64-column slices.  Results
+ *                     are bitwise equal to those of 64-column tiles.
  *   "far_fp64_min_p": smallest order p at which FP32-bulk modes evaluate the
  *                     equivalent-surface terms in FP64 (default 10; 2..17,
  *                     17 = never).
@@ -219,6 +222,12 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     both adding into the zeroed output with atomics; each
  *                     output is then the sum of two terms, so results stay
  *                     bitwise reproducible.  0: one block per tile.
+ *   "near_fork":      4 (default): near field (P2P) and far field (L2P,
+ *                     M2P) of each leaf are summed by one kernel at the end
+ *                     of the evaluation.  0..3: the near field runs as its
+ *                     own kernel on a second stream, forked after the points
+ *                     are gathered (0), after P2M (2), before M2L (1) or
+ *                     after M2L (3), and joins before the far field.
  * EINVAL for an unknown key or value. */
 kifmm_status kifmm_set_tuning(const char* key, int32_t value);
 

@@ -313,7 +313,7 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
     return KIFMM_OK;
   }
   if (std::strcmp(key, "near_fork") == 0) {
-    if (value < 0 || value > 2) return fail(KIFMM_EINVAL, "set_tuning: near_fork must be 0, 1 or 2");
+    if (value < 0 || value > 4) return fail(KIFMM_EINVAL, "set_tuning: near_fork must be 0..4");
     set_near_fork(value);
     return KIFMM_OK;
   }

@@ -1628,8 +1628,13 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64,
 
 // Where the near field forks off the evaluation stream: 0 right after the
 // gather, 2 after P2M (it then overlaps the latency-bound M2M / C2E chain
-// rather than P2M), 1 just before M2L.
-static int g_near_fork = 0;
+// rather than P2M), 1 just before M2L, 3 right after M2L (overlapping the
+// L2L / C2E chain); 4 (default): no fork, near and far field as one kernel
+// at the end.  Measured on 1M points: the concurrent near field takes the
+// compute units the chain kernels would use, so the forked schedules are no
+// faster than running everything in order, and the one merged kernel saves
+// the far field's own pass over the leaves.
+static int g_near_fork = 4;
 void set_near_fork(int v) { g_near_fork = v; }
 
 // Per-device auxiliary stream and fork/join events of the pipeline (default
@@ -1703,8 +1708,10 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.pot = W.pot;
   base.ntgt = F.ntgt;
   // The near field needs only the gathered charges; it runs on the
-  // auxiliary stream, forked either here or just before M2L (g_near_fork),
-  // and is joined before the far field.
+  // auxiliary stream, forked after the gather (g_near_fork 0), after P2M (2),
+  // before M2L (1) or after it (3), and is joined before the far field.  With
+  // g_near_fork 4 near and far field run as one kernel at the end.
+  const bool merged_leaf = g_near_fork == 4;
   auto fork_near = [&]() {
     HIPCHECK(hipEventRecord(aux.forked, s));
     HIPCHECK(hipStreamWaitEvent(aux.stream, aux.forked, 0));
@@ -1829,6 +1836,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
         run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, nullptr);
     }
   }
+  if (g_near_fork == 3) fork_near();
   {
     PhaseScope ps(PH_P2L, s);
     P2PArgs<T> a = base;
@@ -1849,8 +1857,9 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     }
   }
   {
-    // join the near field, then add the far field (L2P + M2P)
-    HIPCHECK(hipStreamWaitEvent(s, aux.joined, 0));
+    // join the near field, then add the far field (L2P + M2P); or both in
+    // one kernel
+    if (!merged_leaf) HIPCHECK(hipStreamWaitEvent(s, aux.joined, 0));
     PhaseScope ps(PH_FAR, s);
     P2PArgs<T> a = base;
     a.work = F.leaf_boxes;
@@ -1859,7 +1868,8 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.l2_off = F.w_off;
     a.l2_items = F.w_items;
     const bool far64 = sizeof(T) == 4 && O.p >= g_far_fp64_min_p;
-    run_p2p_rc<T, MODE_FAR, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
+    if (merged_leaf) run_p2p_rc<T, MODE_LEAF, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
+    else run_p2p_rc<T, MODE_FAR, 32>(a, F.n_leaf, n_rhs, far64, s, ps);
   }
   {
     PhaseScope ps(PH_SCATTER, s);

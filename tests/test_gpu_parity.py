@@ -244,3 +244,30 @@ def test_wide_m2l_tiles_equal_narrow(precision):
     np.testing.assert_array_equal(wide, narrow)
     want = oracle(name, x, q, tgt, p, **kw)
     assert rel(wide, want) < TOL32
+
+
+@pytest.mark.parametrize("fork", [0, 1, 2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_near_field_schedules(fork, precision):
+    """Every place of the near field in the schedule gives the oracle's
+    potentials: the default (near and far field summed by one kernel at the
+    end) and the near field as its own kernel on a second stream, forked after
+    the gather, after P2M, before or after M2L.  The forked schedules differ
+    from the default only in the rounding of the near + far sum; among
+    themselves they only move the same kernels between streams, so they agree
+    bitwise."""
+    name = "sphere12k_nc32_p6"
+    x, q, tgt, p, kw = _case(name)
+    tree = K.Tree(x, tgt, **kw)
+    merged = gpu_eval(tree, p, q, precision)
+    K.set_tuning("near_fork", fork)
+    try:
+        got = gpu_eval(tree, p, q, precision)
+        K.set_tuning("near_fork", 0)
+        first = gpu_eval(tree, p, q, precision)
+    finally:
+        K.set_tuning("near_fork", 4)
+    np.testing.assert_array_equal(got, first)
+    assert rel(got, merged) < (1e-13 if precision == "fp64" else 1e-6)
+    want = oracle(name, x, q, tgt, p, **kw)
+    assert rel(got, want) < TOL[precision]
