@@ -147,7 +147,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--direct-sample", type=int, default=200)
-    ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128)")
+    ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128/192)")
+    ap.add_argument("--m2l-pair-fill", type=int, default=-1,
+                    help="problems whose M2L tiles are less full than this (percent) run M2L pair by pair")
     ap.add_argument("--near-fork", type=int, default=-1,
                     help="fork the near field after the gather (0) or before M2L (1)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -166,6 +168,8 @@ def main():
 
     if args.m2l_tile:
         K.set_tuning("m2l_tile_cols", args.m2l_tile)
+    if args.m2l_pair_fill >= 0:
+        K.set_tuning("m2l_pair_fill", args.m2l_pair_fill)
     if args.near_fork >= 0:
         K.set_tuning("near_fork", args.near_fork)
     if args.copy_probe:
@@ -288,7 +292,19 @@ def main():
         far_pairs += w[2]
     flops_m2l = 2.0 * pn * pn * v_pairs * n_rhs
     leaf_pairs = (near_pairs + far_pairs) * n_rhs
-    if dom == "m2l":
+    pair_stage = launches.get("m2l_pair", 0.0) > 0
+    if dom == "m2l_pair" or (dom == "m2l" and pair_stage):
+        # sparse (adaptive) problems run M2L pair by pair: the algorithmic
+        # flops over the whole M2L stage (gathered tiles, pair tiles, pair sums)
+        m2l_kind = precision.split("m2l_")[-1]
+        peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
+                "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
+        issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
+        t_stage = (ms["m2l"] + ms["m2l_pair"]) * 1e-3
+        roof = {"kernel": "M2L stage (gemm_kernel gathered + pair tiles, m2l_pair_sum_kernel)",
+                "bound": "mfma", "achieved": flops_m2l / t_stage / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "issued_frac": issued * flops_m2l / t_stage / peak}
+    elif dom == "m2l":
         # algorithmic flops (one product per V-list pair), against the peak of
         # the instruction the path issues; split-BF16 issues 3 (5) products
         m2l_kind = precision.split("m2l_")[-1]

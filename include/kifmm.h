@@ -217,6 +217,20 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     in FP32 (FP32, BF16 and FP16 products) moves its sums
  *                     into FP64 after every operator step (default 10; 17 =
  *                     never).
+ *   "m2l_pair_fill":  percent, default 40.  A problem whose M2L tiles would
+ *                     be less full than this (V-list pairs over 64 tile
+ *                     columns x the union of the tile's offsets: adaptive
+ *                     trees of surfaces) runs M2L pair by pair instead: tiles
+ *                     of pairs that share one offset write each product to a
+ *                     pair buffer (n_pairs x n_rhs x ld values, ld = n
+ *                     rounded up to 32, allocated on the first evaluation),
+ *                     then each target sums its pairs in offset order.  The
+ *                     percentage applies at ld = 160 (p = 6) and scales with
+ *                     sqrt(ld / 160).  Decided per problem, so batches and
+ *                     multi-RHS runs match single runs bitwise, unless the
+ *                     pair buffer would pass 64 GiB (then every problem of
+ *                     that evaluation runs gathered tiles).  0: never;
+ *                     101: always (within the cap).
  *   "m2l_split":      1 (default): every M2L tile runs as two blocks, one for
  *                     the offsets with even x component and one for the odd,
  *                     both adding into the zeroed output with atomics; each

@@ -63,9 +63,28 @@ static int plan_width(int n_rhs) { return std::max(1, 64 / n_rhs); }
 static std::atomic<int> g_m2l_tile_cols{64};
 static int m2l_plan_width(int n_rhs) { return std::max(1, g_m2l_tile_cols.load() / n_rhs); }
 static std::atomic<int> g_m2l_split{1};
+static std::atomic<int> g_m2l_pair_fill{40};  // percent, at operators of 160 rows
+// Tile-fill threshold below which a problem runs M2L pair by pair.  The pair
+// scheme moves n_rhs x ld values per pair through HBM on top of the products
+// the tiles also compute, so it pays at higher fills as the operators grow:
+// the threshold scales with sqrt(ld / 160) (measured crossovers of the split
+// modes on surface trees: ~0.4 at p = 6, ~0.57 at p = 8, ~0.73 at p = 10).
+static double pair_fill(int n) {
+  const int v = g_m2l_pair_fill.load();
+  if (v >= 101) return 2.0;  // always
+  const int ld = (n + 31) / 32 * 32;
+  return v / 100.0 * std::sqrt(ld / 160.0);
+}
+// The pair buffer holds n_pairs x n_rhs x ld values of up to 8 bytes; plans
+// keep it under 64 GiB (beyond that every problem runs gathered tiles).
+static int64_t max_pairs(int n, int n_rhs) {
+  const int64_t ld = (n + 31) / 32 * 32;
+  return (int64_t(64) << 30) / (ld * n_rhs * 8);
+}
 // a cached plan is reused only if it was cut the way the tuning asks now
-static bool plan_current(const HostForest& F, int TB, int TBm) {
-  return F.dc2e.back().TB == TB && F.m2l.TB == TBm && F.m2l.split == (g_m2l_split.load() != 0);
+static bool plan_current(const HostForest& F, int TB, int TBm, int n, int n_rhs) {
+  return F.dc2e.back().TB == TB && F.m2l.TB == TBm && F.m2l.split == (g_m2l_split.load() != 0) &&
+         F.pair_fill == pair_fill(n) && F.max_pairs == max_pairs(n, n_rhs);
 }
 
 template <class F>
@@ -212,10 +231,12 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
     if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate: null charges or potentials");
     auto* t = const_cast<kifmm_tree*>(tree);
     const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
-    if (!t->state || t->state_n != ops->host->n || !plan_current(*t->state->host, TB, TBm)) {
+    const int n = ops->host->n;
+    if (!t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs)) {
       t->state.reset(new EvalState());
       const HostTree* one = t->host.get();
-      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0));
+      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0,
+                                        pair_fill(n), max_pairs(n, n_rhs)));
       t->state_n = ops->host->n;
     }
     const void* q[1] = {charges};
@@ -241,13 +262,14 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
     {
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto& slot = g_batches[key];
-      if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1))) slot.reset();
+      const int n = ops->host->n;
+      if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1), n, 1)) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);
         for (int k = 0; k < n_prob; ++k) hts[k] = trees[k]->host.get();
         auto s = std::make_unique<EvalState>();
         s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1),
-                                   g_m2l_split.load() != 0));
+                                   g_m2l_split.load() != 0, pair_fill(n), max_pairs(n, 1)));
         slot = std::move(s);
       }
       st = slot.get();
@@ -272,7 +294,8 @@ kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n
       if (!std::isfinite(q[i])) raise(KIFMM_EINVAL, "evaluate_simple: non-finite charge");
     EvalState st;
     const HostTree* one = ht.get();
-    st.host.reset(build_forest(&one, 1, *ho, plan_width(1), m2l_plan_width(1), g_m2l_split.load() != 0));
+    st.host.reset(build_forest(&one, 1, *ho, plan_width(1), m2l_plan_width(1), g_m2l_split.load() != 0,
+                              pair_fill(ho->n), max_pairs(ho->n, 1)));
     OpsCache oc;
     evaluate_simple_host(st, *ho, oc, q, n_src, pot, n_tgt);
   });
@@ -305,6 +328,11 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
     if (value != 64 && value != 128 && value != 192)
       return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64, 128 or 192");
     g_m2l_tile_cols = value;
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "m2l_pair_fill") == 0) {
+    if (value < 0 || value > 101) return fail(KIFMM_EINVAL, "set_tuning: m2l_pair_fill must be 0..101");
+    g_m2l_pair_fill = value;
     return KIFMM_OK;
   }
   if (std::strcmp(key, "m2l_split") == 0) {

@@ -92,6 +92,8 @@ struct DevWork {
   size_t col_bytes = 0;
   void* split = nullptr;       // split-precision M2L operand, up to 3 16-bit parts per element
   size_t split_bytes = 0;
+  void* pairs = nullptr;       // pair-by-pair M2L products [n_pairs][n_rhs][ld]
+  size_t pair_bytes = 0;
   std::vector<void*> allocs;
   ~DevWork() {
     for (void* p : allocs) (void)hipFree(p);
@@ -116,6 +118,11 @@ struct DevForest {
   std::vector<int32_t*> m2m_sum;     // per level [n][9], see HostForest
   std::vector<int32_t> n_m2m_sum;
   DevPlan m2l;
+  // pair-by-pair M2L of sparse problems (see HostForest::m2l_pair)
+  DevPlan m2l_pair;
+  int32_t *pair_tgt = nullptr, *pair_off = nullptr, *pair_items = nullptr;
+  int32_t n_pair_tgt = 0;
+  int64_t n_pairs = 0;
   std::vector<void*> allocs;
   std::map<std::pair<int, int>, DevWork*> work;  // (fp64, n_rhs)
   // the last captured evaluation and what it was captured for
@@ -230,6 +237,14 @@ static DevForest* upload_forest(const HostForest& F, int n) {
     for (auto& p : F.l2l) D->l2l.push_back(upload_plan(A, p, F.nbox));
     for (auto& p : F.dc2e) D->dc2e.push_back(upload_plan(A, p, F.nbox));
     D->m2l = upload_plan(A, F.m2l, F.nbox);
+    D->m2l_pair = upload_plan(A, F.m2l_pair, F.nbox);
+    D->n_pairs = F.n_pairs;
+    D->n_pair_tgt = int32_t(F.pair_tgt.size());
+    if (D->n_pair_tgt > 0) {
+      D->pair_tgt = dev_upload<int32_t>(A, F.pair_tgt);
+      D->pair_off = dev_upload<int32_t>(A, F.pair_off);
+      D->pair_items = dev_upload<int32_t>(A, F.pair_items);
+    }
   } catch (...) {
     delete D;
     throw;
@@ -398,6 +413,14 @@ static void ensure_split(DevForest& F, DevWork* W) {
   HIPCHECK(hipMemset(W->split, 0, W->split_bytes));
 }
 
+// The pair buffer of the pair-by-pair M2L, allocated on first use (outside
+// graph capture).
+static void ensure_pairs(DevForest& F, DevWork* W) {
+  if (W->pairs || F.n_pairs == 0) return;
+  W->pair_bytes = size_t(F.n_pairs) * W->n_rhs * F.ld * (W->fp64 ? 8 : 4);
+  W->pairs = dev_alloc<unsigned char>(W->allocs, W->pair_bytes);
+}
+
 // ------------------------------------------------------------------------
 // profiling: HIP events around each phase on the evaluation stream
 // ------------------------------------------------------------------------
@@ -406,10 +429,10 @@ static void ensure_split(DevForest& F, DevWork* W) {
 // alone; zeroing its output and the FP16 density scale are "m2l_prep").  While profiling
 // is on, the near field runs on the evaluation stream instead of the
 // auxiliary one, so no two phases overlap and each one's events time it alone.
-enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_M2L_PREP, PH_M2L, PH_P2L, PH_L2L, PH_DC2E,
-             PH_NEAR, PH_FAR, PH_SCATTER, PH_N };
-static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "m2l_prep", "m2l", "p2l",
-                                        "l2l", "dc2e", "near", "far", "scatter"};
+enum Phase { PH_GATHER, PH_P2M, PH_M2M, PH_UC2E, PH_M2L_PREP, PH_M2L, PH_M2L_PAIR, PH_P2L, PH_L2L,
+             PH_DC2E, PH_NEAR, PH_FAR, PH_SCATTER, PH_N };
+static const char* kPhaseNames[PH_N] = {"gather", "p2m", "m2m", "uc2e", "m2l_prep", "m2l", "m2l_pair",
+                                        "p2l", "l2l", "dc2e", "near", "far", "scatter"};
 
 struct Profiler {
   bool on = false;
@@ -554,6 +577,47 @@ __global__ void absmax_kernel64(const double2* __restrict__ p, int64_t n2, unsig
     m = fmaxf(m, float(fmax(fabs(v.x), fabs(v.y))));
   }
   block_max_to(m, out);
+}
+
+// Pair-by-pair M2L, second half: the downward check potential of each target
+// of a sparse problem is the sum of its pairs' products (pair buffer columns
+// of n_rhs * ld elements), taken in the order the plan lists them (by
+// offset), in FP64, rounded once.  The targets' columns receive nothing else
+// before P2L, so the sum is stored.  One thread per 16-byte unit of a
+// target's columns; eight pairs' loads are issued before they are added (in
+// order).  Grid-stride over (target, unit).
+template <class T>
+__global__ void m2l_pair_sum_kernel(const int32_t* __restrict__ tgt, const int32_t* __restrict__ off,
+                                    const int32_t* __restrict__ items, int ntgt, int64_t units,
+                                    const uint4* __restrict__ pairs, uint4* __restrict__ out) {
+  constexpr int E = 16 / sizeof(T), U = 8;
+  const int64_t tot = int64_t(ntgt) * units;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < tot;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t k = i / units, w = i - k * units;
+    double acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    const int e0 = off[k], e1 = off[k + 1];
+    for (int b = e0; b < e1; b += U) {
+      uint4 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u < e1) v[u] = pairs[int64_t(items[b + u]) * units + w];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (b + u < e1) {
+          const T* x = reinterpret_cast<const T*>(&v[u]);
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc[e] += double(x[e]);
+        }
+    }
+    uint4 r;
+    T* y = reinterpret_cast<T*>(&r);
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = T(acc[e]);
+    out[int64_t(tgt[k]) * units + w] = r;
+  }
 }
 
 // M2M, second half: the upward check potential of each parent is the sum of
@@ -1018,30 +1082,35 @@ template <> struct GT<GM_F32> {
   static constexpr int KC = 32, NB = 1;
   // output layout of 16x16 products: lane l, register v -> D[row(l,v)][l%16]
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static constexpr bool ROWS4 = true;  // a lane's four registers are consecutive rows
 };
 template <> struct GT<GM_F64> {
   using TA = double;
   using acc = f64x4;
   static constexpr int KC = 16, NB = 1;
   __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+  static constexpr bool ROWS4 = false;
 };
 template <> struct GT<GM_BF3> {
   using TA = __bf16;
   using acc = f32x4;
   static constexpr int KC = 32, NB = 2;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static constexpr bool ROWS4 = true;
 };
 template <> struct GT<GM_BF5> {
   using TA = __bf16;
   using acc = f32x4;
   static constexpr int KC = 32, NB = 3;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static constexpr bool ROWS4 = true;
 };
 template <> struct GT<GM_H3> {
   using TA = _Float16;
   using acc = f32x4;
   static constexpr int KC = 32, NB = 2;
   __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+  static constexpr bool ROWS4 = true;
 };
 
 struct GemmArgs {
@@ -1530,20 +1599,35 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
 #pragma unroll
         for (int i = 0; i < RBW; ++i) {
           if (wr * RBW + i < nrb) {
+            // summed in the wider of the accumulator and output types
+            using TAcc = typename std::conditional<(sizeof(TO) > sizeof(acc[0][0][0])), TO,
+                                                   decltype(acc[0][0][0] + 0)>::type;
+            TAcc val[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int row = row0 + (wr * RBW + i) * 16 + G::row(lane, v);
-              // summed in the wider of the accumulator and output types
-              using TAcc = typename std::conditional<(sizeof(TO) > sizeof(acc[0][0][0])), TO,
-                                                     decltype(acc[0][0][0] + 0)>::type;
-              TAcc val = TAcc(acc[i][c][v]);
-              if constexpr (FLUSH) val = TAcc(acc64[i][c][v] + double(acc[i][c][v]));
-              if constexpr (MODE == GM_H3) val *= TAcc(out_scale);
-              if (a.atomic) {
-                unsafeAtomicAdd(o + row, TO(val));
-              } else {
-                if (a.accumulate) val += TAcc(o[row]);
-                o[row] = TO(val);
+              val[v] = TAcc(acc[i][c][v]);
+              if constexpr (FLUSH) val[v] = TAcc(acc64[i][c][v] + double(acc[i][c][v]));
+              if constexpr (MODE == GM_H3) val[v] *= TAcc(out_scale);
+            }
+            const int rbase = row0 + (wr * RBW + i) * 16;
+            if (a.atomic) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) unsafeAtomicAdd(o + rbase + G::row(lane, v), TO(val[v]));
+            } else if constexpr (G::ROWS4 && sizeof(TO) == 4) {
+              // the lane's four rows are consecutive: one 16-byte access
+              f32x4* o4 = reinterpret_cast<f32x4*>(o + rbase + G::row(lane, 0));
+              f32x4 w;
+              if (a.accumulate) w = *o4;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) w[v] = a.accumulate ? float(val[v] + TAcc(w[v])) : float(val[v]);
+              *o4 = w;
+            } else {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int row = rbase + G::row(lane, v);
+                TAcc x = val[v];
+                if (a.accumulate) x += TAcc(o[row]);
+                o[row] = TO(x);
               }
             }
           }
@@ -1808,32 +1892,54 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       if (prec == KIFMM_M2L_BF16X3) split_in(std::integral_constant<int, GM_BF3>(), up_eq, nullptr);
       if (prec == KIFMM_M2L_BF16X5) split_in(std::integral_constant<int, GM_BF5>(), up_eq, nullptr);
     }
-    PhaseScope ps(PH_M2L, s);
     const bool fp64_sum = O.p >= g_m2l_fp64_sum_min_p;
-    auto run_m2l_impl = [&](auto mode_tag, const void* opa, const unsigned* amax) {
-      constexpr int MODE = decltype(mode_tag)::value;
-      constexpr bool split = !(MODE == GM_F32 || MODE == GM_F64);
-      using TIn = typename std::conditional<split, typename GT<MODE>::TA, T>::type;
-      const TIn* in = split ? static_cast<const TIn*>(W.split) : reinterpret_cast<const TIn*>(m2l_in);
-      constexpr int64_t parts = split ? 2 : 1;
-      if (fp64_sum)
-        run_gemm<MODE, TIn, T, 2>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
-      else
-        run_gemm<MODE, TIn, T, 1>(F.m2l, opa, parts * nn, ld, F.nbox, n_rhs, in, dn_chk, true, s, ps, amax);
+    // one M2L plan: the gathered tiles (adding into dn_chk with atomics), or
+    // the pair tiles (storing into the pair buffer)
+    auto run_m2l = [&](const DevPlan& P, T* out, PhaseScope& ps) {
+      auto run_m2l_impl = [&](auto mode_tag, const void* opa, const unsigned* amax) {
+        constexpr int MODE = decltype(mode_tag)::value;
+        constexpr bool split = !(MODE == GM_F32 || MODE == GM_F64);
+        using TIn = typename std::conditional<split, typename GT<MODE>::TA, T>::type;
+        const TIn* in = split ? static_cast<const TIn*>(W.split) : reinterpret_cast<const TIn*>(m2l_in);
+        constexpr int64_t parts = split ? 2 : 1;
+        if (fp64_sum)
+          run_gemm<MODE, TIn, T, 2>(P, opa, parts * nn, ld, F.nbox, n_rhs, in, out, false, s, ps, amax);
+        else
+          run_gemm<MODE, TIn, T, 1>(P, opa, parts * nn, ld, F.nbox, n_rhs, in, out, false, s, ps, amax);
+      };
+      const void* op32 = check_form ? static_cast<const void*>(O.m2lc32) : static_cast<const void*>(O.m2l32);
+      const void* oph = check_form ? O.m2lc_h : O.m2l_h;
+      if (prec == KIFMM_FP64) {
+        run_gemm<GM_F64, T, T, 1>(P, O.m2l64, nn, ld, F.nbox, n_rhs, m2l_in, out, false, s, ps);
+      } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
+        run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, nullptr);
+      } else if (f16) {
+        run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, W.absmax);
+      } else if constexpr (sizeof(T) == 4) {
+        if (prec == KIFMM_M2L_BF16X3)
+          run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_b, nullptr);
+        else
+          run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, nullptr);
+      }
     };
-    const void* op32 = check_form ? static_cast<const void*>(O.m2lc32) : static_cast<const void*>(O.m2l32);
-    const void* oph = check_form ? O.m2lc_h : O.m2l_h;
-    if (prec == KIFMM_FP64) {
-      run_gemm<GM_F64, T, T, 1>(F.m2l, O.m2l64, nn, ld, F.nbox, n_rhs, m2l_in, dn_chk, true, s, ps);
-    } else if (prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32) {
-      run_m2l_impl(std::integral_constant<int, GM_F32>(), op32, nullptr);
-    } else if (f16) {
-      run_m2l_impl(std::integral_constant<int, GM_H3>(), oph, W.absmax);
-    } else if constexpr (sizeof(T) == 4) {
-      if (prec == KIFMM_M2L_BF16X3)
-        run_m2l_impl(std::integral_constant<int, GM_BF3>(), O.m2l_b, nullptr);
-      else
-        run_m2l_impl(std::integral_constant<int, GM_BF5>(), O.m2l_b, nullptr);
+    {
+      PhaseScope ps(PH_M2L, s);
+      run_m2l(F.m2l, dn_chk, ps);
+    }
+    if (F.m2l_pair.ntile > 0) {
+      // sparse problems: one product per pair, then each target's sum
+      PhaseScope ps(PH_M2L_PAIR, s);
+      if (W.pairs == nullptr) raise(KIFMM_EINVAL, "evaluate: pair buffer missing");
+      T* pairs = static_cast<T*>(W.pairs);
+      run_m2l(F.m2l_pair, pairs, ps);
+      const int64_t units = int64_t(n_rhs) * ld * int64_t(sizeof(T)) / 16;
+      const int64_t tot = int64_t(F.n_pair_tgt) * units;
+      const unsigned nblk = unsigned(std::min<int64_t>((tot + 255) / 256, 65536));
+      hipLaunchKernelGGL(m2l_pair_sum_kernel<T>, dim3(nblk), dim3(256), 0, s, F.pair_tgt, F.pair_off,
+                         F.pair_items, F.n_pair_tgt, units, reinterpret_cast<const uint4*>(pairs),
+                         reinterpret_cast<uint4*>(dn_chk));
+      LAUNCHCHECK("m2l_pair_sum_kernel");
+      ps.launches++;
     }
   }
   if (g_near_fork == 3) fork_near();
@@ -1915,6 +2021,7 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
   DevWork* W = work_for(F, fp64, n_rhs);
   if (need.bf16 || need.f16) ensure_split(F, W);
+  ensure_pairs(F, W);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto launch_all = [&]() {
     if (fp64) {

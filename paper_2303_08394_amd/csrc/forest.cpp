@@ -53,7 +53,7 @@ Plan new_plan(int TB) {
 }  // namespace
 
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
-                         bool split) {
+                         bool split, double pair_fill, int64_t max_pairs) {
   auto* Fp = new HostForest();
   HostForest& F = *Fp;
   F.nprob = n;
@@ -240,9 +240,46 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       if (mask[x] != mask[y]) return mask[x] > mask[y];
       return x < y;
     });
-    auto tiles = group_tiles(tg, TBm, [&](int32_t g) {
-      return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g];
-    });
+    auto class_key = [&](int32_t g) { return int64_t(F.box_geo[4 * size_t(g) + 3]) * 8 + F.box_octant[g]; };
+    // Fill of each problem's own tiles: V-list pairs over (union of the
+    // tile's offsets) x tile width, for tiles of 64 boxes whatever TBm is.  A
+    // problem below pair_fill runs M2L pair by pair; the choice depends on
+    // the problem alone (not on the batch it is in, nor on the number of
+    // right-hand sides), so results match across those bitwise.
+    constexpr int kFillTB = 64;
+    auto prob_of = [&](int32_t g) {
+      return int(std::upper_bound(F.box_off.begin(), F.box_off.end(), g) - F.box_off.begin()) - 1;
+    };
+    std::vector<char> as_pairs(n, 0);
+    if (pair_fill > 0.0) {
+      std::vector<std::vector<int32_t>> per(n);
+      for (int32_t g : tg) per[prob_of(g)].push_back(g);
+      for (int k = 0; k < n; ++k) {
+        int64_t useful = 0, slots = 0;
+        for (auto& tile : group_tiles(per[k], kFillTB, class_key)) {
+          std::vector<uint64_t> u((kNumM2L + 63) / 64, 0);
+          for (int32_t g : tile) {
+            useful += int64_t(vl[g].size());
+            for (size_t w = 0; w < u.size(); ++w) u[w] |= mask[g][w];
+          }
+          int64_t cnt = 0;
+          for (uint64_t w : u) cnt += __builtin_popcountll(w);
+          slots += cnt * kFillTB;
+        }
+        as_pairs[k] = slots > 0 && double(useful) < pair_fill * double(slots);
+      }
+      int64_t np = 0;
+      for (int32_t g : tg)
+        if (as_pairs[prob_of(g)]) np += int64_t(vl[g].size());
+      if (np > max_pairs) std::fill(as_pairs.begin(), as_pairs.end(), 0);
+    }
+    std::vector<int32_t> tg_pairs;
+    {
+      std::vector<int32_t> dense;
+      for (int32_t g : tg) (as_pairs[prob_of(g)] ? tg_pairs : dense).push_back(g);
+      tg.swap(dense);
+    }
+    auto tiles = group_tiles(tg, TBm, class_key);
     // Step order inside a tile: by the parity of the offset, then by
     // operator.  The targets of one tile share their octant, so the parity of
     // the offset fixes the parity class of every source box the step reads;
@@ -308,6 +345,70 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
     }
     F.m2l.atomic = true;
     F.m2l.split = split;
+
+    // Pair-by-pair M2L of the sparse problems: pairs sorted by offset, then
+    // target; tiles of TBm pairs of one offset (one step each); pair p writes
+    // column p of the pair buffer.  The offsets are dealt to 8 queues
+    // (fewest tiles first) and the queues interleaved, so that consecutive
+    // blocks, which go to different XCDs, take their operators from
+    // different queues and each operator is read by one XCD's L2.
+    F.m2l_pair = new_plan(TBm);
+    F.pair_fill = pair_fill;
+    F.max_pairs = max_pairs;
+    struct PairE {
+      int32_t op, t, s;
+    };
+    std::vector<PairE> pe;
+    for (int32_t g : tg_pairs)
+      for (auto& e : vl[g]) pe.push_back({e.first, g, e.second});
+    std::sort(pe.begin(), pe.end(), [](const PairE& x, const PairE& y) {
+      return x.op != y.op ? x.op < y.op : x.t < y.t;
+    });
+    F.n_pairs = int64_t(pe.size());
+    if (F.n_pairs > (int64_t(1) << 31) - 1) raise(KIFMM_EUNSUPPORTED, "forest: too many M2L pairs");
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> per_op(kNumM2L);  // tile ranges in pe
+    for (size_t i = 0; i < pe.size();) {
+      size_t j = i;
+      while (j < pe.size() && pe[j].op == pe[i].op && j - i < size_t(TBm)) ++j;
+      per_op[pe[i].op].push_back({int32_t(i), int32_t(j)});
+      i = j;
+    }
+    std::vector<int32_t> op_order(kNumM2L);
+    for (int o = 0; o < kNumM2L; ++o) op_order[o] = o;
+    std::stable_sort(op_order.begin(), op_order.end(),
+                     [&](int32_t x, int32_t y) { return per_op[x].size() > per_op[y].size(); });
+    std::array<std::vector<std::pair<int32_t, int32_t>>, 8> pq;
+    std::array<size_t, 8> load{};
+    for (int32_t o : op_order) {
+      if (per_op[o].empty()) continue;
+      int qi = int(std::min_element(load.begin(), load.end()) - load.begin());
+      for (auto& r : per_op[o]) pq[qi].push_back(r);
+      load[qi] += per_op[o].size();
+    }
+    std::array<size_t, 8> qpos{};
+    for (bool any = true; any;) {
+      any = false;
+      for (int qi = 0; qi < 8; ++qi)
+        if (qpos[qi] < pq[qi].size()) {
+          auto r = pq[qi][qpos[qi]++];
+          std::vector<int32_t> cols, srcs;
+          for (int32_t i = r.first; i < r.second; ++i) {
+            cols.push_back(i);
+            srcs.push_back(pe[i].s);
+          }
+          add_tile(F.m2l_pair, cols, {pe[r.first].op}, {srcs});
+          any = true;
+        }
+    }
+    // per target: its pairs in offset order
+    std::map<int32_t, std::vector<int32_t>> of_tgt;
+    for (size_t i = 0; i < pe.size(); ++i) of_tgt[pe[i].t].push_back(int32_t(i));
+    F.pair_off.push_back(0);
+    for (auto& kv : of_tgt) {
+      F.pair_tgt.push_back(kv.first);
+      F.pair_items.insert(F.pair_items.end(), kv.second.begin(), kv.second.end());
+      F.pair_off.push_back(int32_t(F.pair_items.size()));
+    }
   }
   return Fp;
 }

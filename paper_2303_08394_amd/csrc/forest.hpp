@@ -59,6 +59,18 @@ struct HostForest {
   std::vector<Plan> m2m, uc2e, l2l, dc2e;
   std::vector<std::vector<int32_t>> m2m_sum;
   Plan m2l;
+  // Problems whose M2L tiles would be sparse (the tiles' fill, V-list pairs
+  // over tile columns x steps, below pair_fill: adaptive trees of surfaces)
+  // run M2L pair by pair instead: m2l_pair has one step per tile, TBm
+  // (target, source) pairs of one offset, and writes pair p's product to
+  // column p of a pair buffer; then each target's check potential is the sum
+  // of its pairs (pair_items[pair_off[k] .. pair_off[k + 1]) for target
+  // pair_tgt[k]), in the order of the offsets.
+  Plan m2l_pair;
+  std::vector<int32_t> pair_tgt, pair_off, pair_items;
+  int64_t n_pairs = 0;
+  double pair_fill = 0.0;          // the threshold the plans were built for
+  int64_t max_pairs = 0;           // and the pair count cap
   // statistics of the lists (for work counts)
   int64_t n_u_pairs = 0, n_v_pairs = 0, n_w_pairs = 0, n_x_pairs = 0;
   int64_t p2p_interactions = 0;  // sum over U pairs of n_tgt(B) * n_src(A)
@@ -66,8 +78,10 @@ struct HostForest {
 
 // Builds the forest of `n` trees for operator set `ops`: plan width TB boxes
 // per tile for M2M, L2L and the solves, TBm for M2L.  With split, every M2L
-// tile is run as two blocks (even and odd x offsets).
+// tile is run as two blocks (even and odd x offsets).  Problems whose M2L
+// tiles fill less than pair_fill of their slots run M2L pair by pair, unless
+// that makes more than max_pairs pairs (then none does).
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
-                         bool split);
+                         bool split, double pair_fill, int64_t max_pairs);
 
 }  // namespace kifmm

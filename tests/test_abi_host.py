@@ -172,3 +172,29 @@ def test_error_paths():
     assert L.kifmm_evaluate(t.handle, ops.handle, C.c_void_p(8), 1, C.c_void_p(8), 1, 9, None) == 1
     assert L.kifmm_evaluate(t.handle, ops.handle, C.c_void_p(8), 65, C.c_void_p(8), 1, 1, None) == 4
     assert L.kifmm_tree_export_list(t.handle, 7, None, None) == 1
+
+
+def test_tuning_keys_validated():
+    """Every tuning key accepts its documented values and rejects others
+    (host only: a value takes effect at the next evaluate)."""
+    good = {"m2l_tile_cols": (64, 128, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
+            "near_fork": (0, 1, 2, 3, 4), "graph": (0, 1), "m2l_fp64_sum_min_p": (2, 10, 17),
+            "m2l_check_min_p": (2, 10, 17), "far_fp64_min_p": (2, 10, 17)}
+    bad = {"m2l_tile_cols": (0, 96, 256), "m2l_split": (2, -1), "m2l_pair_fill": (-1, 102),
+           "near_fork": (-1, 5), "graph": (2,), "m2l_fp64_sum_min_p": (1, 18),
+           "m2l_check_min_p": (1, 18), "far_fp64_min_p": (1, 18)}
+    defaults = {"m2l_tile_cols": 64, "m2l_split": 1, "m2l_pair_fill": 40, "near_fork": 4, "graph": 1,
+                "m2l_fp64_sum_min_p": 10, "m2l_check_min_p": 10, "far_fp64_min_p": 10}
+    try:
+        for k, vs in good.items():
+            for v in vs:
+                K.set_tuning(k, v)
+        for k, vs in bad.items():
+            for v in vs:
+                with pytest.raises(K.KifmmError):
+                    K.set_tuning(k, v)
+        with pytest.raises(K.KifmmError, match="unknown"):
+            K.set_tuning("no_such_key", 1)
+    finally:
+        for k, v in defaults.items():
+            K.set_tuning(k, v)

@@ -271,3 +271,55 @@ def test_near_field_schedules(fork, precision):
     assert rel(got, merged) < (1e-13 if precision == "fp64" else 1e-6)
     want = oracle(name, x, q, tgt, p, **kw)
     assert rel(got, want) < TOL[precision]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "f16x3"])
+def test_m2l_pair_scheme(name, precision):
+    """M2L run pair by pair (one product per V-list pair, then each target's
+    sum in offset order) gives the oracle's potentials, and agrees with the
+    gathered tiles up to the rounding of the sums.  (In FP64 the rounding
+    differences of the check potentials pass through the check-to-equivalent
+    solves, whose pseudo-inverse keeps singular values down to 1e-9 of the
+    largest: measured ~5e-10 on the potentials, bounded by TOL64.)"""
+    x, q, tgt, p, kw = _case(name)
+    tree = K.Tree(x, tgt, **kw)
+    K.set_tuning("m2l_pair_fill", 101)  # every problem pair by pair
+    try:
+        pairs = gpu_eval(tree, p, q, precision)
+        K.set_tuning("m2l_pair_fill", 0)  # every problem in gathered tiles
+        tiles = gpu_eval(tree, p, q, precision)
+    finally:
+        K.set_tuning("m2l_pair_fill", 40)
+    want = oracle(name, x, q, tgt, p, **kw)
+    assert rel(pairs, want) < TOL[precision]
+    assert rel(pairs, tiles) < (TOL64 if precision == "fp64" else 1e-6)
+
+
+def test_batch_mixed_m2l_schemes_equal_individual_runs():
+    """A batch whose problems take different M2L schemes reproduces each
+    problem's single run bitwise (at a 20% threshold the sphere's tiles, ~7%
+    full, run pair by pair and the cube's, ~29% full, as gathered tiles); so
+    do multi-RHS columns run pair by pair."""
+    xs, qs0 = I.sphere_surface(6000, seed=21)
+    xc, qc0 = I.uniform_cube(5000, seed=22)
+    trees = [K.Tree(xs, ncrit=32, max_depth=10), K.Tree(xc, uniform_depth=3, **CUBE)]
+    K.set_tuning("m2l_pair_fill", 20)
+    try:
+        for prec in ("fp32", "bf16x3"):
+            qs = [torch.as_tensor(q[0], dtype=torch.float64, device=DEV) for q in (qs0, qc0)]
+            outs = K.evaluate_batch(trees, ops(5), qs, precision=prec)
+            torch.cuda.synchronize()
+            for t, q, o in zip(trees, (qs0, qc0), outs):
+                single = gpu_eval(t, 5, q, prec)[0]
+                np.testing.assert_array_equal(o.cpu().numpy(), single)
+    finally:
+        K.set_tuning("m2l_pair_fill", 40)
+    qm = np.random.default_rng(23).uniform(-1, 1, (3, 6000))
+    K.set_tuning("m2l_pair_fill", 101)
+    try:
+        m = gpu_eval(trees[0], 5, qm, "fp32")
+        for r in range(3):
+            np.testing.assert_array_equal(m[r], gpu_eval(trees[0], 5, qm[r], "fp32")[0])
+    finally:
+        K.set_tuning("m2l_pair_fill", 40)
