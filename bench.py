@@ -337,6 +337,25 @@ def main():
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
     roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
 
+    if not batch and prob.uniform_depth >= 0 and prob.halfwidth > 0:
+        # the tree's points re-sorted on the device after each point moves to
+        # a fresh position inside its leaf (kifmm_tree_update_points), against
+        # the host build above; the original points are put back afterwards
+        cells = 2 ** prob.uniform_depth
+        lo = np.asarray(prob.center) - prob.halfwidth
+        t = (prob.points - lo) / (2 * prob.halfwidth)
+        c = np.clip(np.floor(t * cells), 0, cells - 1)
+        moved = lo + (c + np.random.default_rng(7).random(c.shape)) / cells * (2 * prob.halfwidth)
+        x_new = torch.as_tensor(moved, dtype=torch.float64, device=dev)
+        x_old = torch.as_tensor(prob.points, dtype=torch.float64, device=dev)
+        tree.update_points(x_new)
+        tree.update_points(x_old)
+        ta = time.perf_counter()
+        for _ in range(3):
+            tree.update_points(x_new)
+            tree.update_points(x_old)
+        result["tree_update_ms"] = (time.perf_counter() - ta) / 6 * 1e3
+
     line = {
         "metric": "FMM evaluate Mpoints/s at 1M pts p=6, rel L2 err<=1e-5; mixed vs plain FP64",
         "value": n_total / t_step / 1e6,

@@ -20,6 +20,11 @@ struct kifmm_tree {
   std::unique_ptr<kifmm::HostTree> host;
   std::unique_ptr<kifmm::EvalState> state;  // single-tree forest + device state
   int state_n = 0;  // operator size the cached forest was built for
+  // points re-sorted on the device and not yet copied into `host`
+  kifmm::PendingPoints* pending = nullptr;
+  ~kifmm_tree() {
+    if (pending) kifmm::pending_free(pending);
+  }
 };
 
 struct kifmm_ops {
@@ -103,6 +108,17 @@ static kifmm_status guard(F&& f) {
   }
 }
 
+// The host copy of a tree, refreshed first from a device point update.
+static const HostTree& host_of(const kifmm_tree* tree) {
+  auto* t = const_cast<kifmm_tree*>(tree);
+  if (t->pending) {
+    pending_to_host(t->pending, *t->host);
+    pending_free(t->pending);
+    t->pending = nullptr;
+  }
+  return *t->host;
+}
+
 static void check_eval_args(const kifmm_tree* tree, const kifmm_ops* ops, int32_t n_rhs,
                             kifmm_precision prec) {
   if (!tree || !ops) raise(KIFMM_EINVAL, "evaluate: null tree or ops handle");
@@ -152,7 +168,8 @@ kifmm_status kifmm_tree_export_boxes(const kifmm_tree* tree, int32_t* level, int
                                      int32_t* parent, int32_t* is_leaf, int64_t* src_range,
                                      int64_t* tgt_range) {
   if (!tree) return fail(KIFMM_EINVAL, "tree_export_boxes: null tree");
-  const HostTree& T = *tree->host;
+  return guard([&] {
+  const HostTree& T = host_of(tree);
   for (int32_t b = 0; b < T.nbox; ++b) {
     if (level) level[b] = T.level[b];
     if (anchor)
@@ -168,7 +185,7 @@ kifmm_status kifmm_tree_export_boxes(const kifmm_tree* tree, int32_t* level, int
       tgt_range[2 * b + 1] = T.tend[b];
     }
   }
-  return KIFMM_OK;
+  });
 }
 
 kifmm_status kifmm_tree_export_list(const kifmm_tree* tree, int32_t which, int64_t* offsets,
@@ -183,10 +200,29 @@ kifmm_status kifmm_tree_export_list(const kifmm_tree* tree, int32_t which, int64
 
 kifmm_status kifmm_tree_export_perm(const kifmm_tree* tree, int64_t* src_perm, int64_t* tgt_perm) {
   if (!tree) return fail(KIFMM_EINVAL, "tree_export_perm: null tree");
-  const HostTree& T = *tree->host;
-  if (src_perm) std::copy(T.sperm.begin(), T.sperm.end(), src_perm);
-  if (tgt_perm) std::copy(T.tperm.begin(), T.tperm.end(), tgt_perm);
-  return KIFMM_OK;
+  return guard([&] {
+    const HostTree& T = host_of(tree);
+    if (src_perm) std::copy(T.sperm.begin(), T.sperm.end(), src_perm);
+    if (tgt_perm) std::copy(T.tperm.begin(), T.tperm.end(), tgt_perm);
+  });
+}
+
+kifmm_status kifmm_tree_update_points(kifmm_tree* tree, const double* src_xyz, const double* tgt_xyz,
+                                      void* hip_stream) {
+  return guard([&] {
+    if (!tree) raise(KIFMM_EINVAL, "tree_update_points: null tree");
+    EvalState* st = tree->state.get();
+    PendingPoints* p = update_points_device(*tree->host, st, src_xyz, tgt_xyz, hip_stream);
+    purge_batches(tree, nullptr);
+    if (tree->pending) pending_free(tree->pending);
+    tree->pending = p;
+    // no forest on this device took the new order in place: refresh the
+    // host copy now, and build the evaluation state from it when needed
+    if (!st || dev_point_view(*st).device != current_device()) {
+      host_of(tree);
+      tree->state.reset();
+    }
+  });
 }
 
 kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out) {
@@ -232,7 +268,14 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
     auto* t = const_cast<kifmm_tree*>(tree);
     const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
     const int n = ops->host->n;
-    if (!t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs)) {
+    bool rebuild = !t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs);
+    if (t->pending && (rebuild || dev_point_view(*t->state).device != current_device())) {
+      // the device-updated points live only in the resident forest: a new
+      // forest (new plans, or another device) is built from the host copy
+      host_of(t);
+      rebuild = true;
+    }
+    if (rebuild) {
       t->state.reset(new EvalState());
       const HostTree* one = t->host.get();
       t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0,
@@ -266,7 +309,7 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
       if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1), n, 1)) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);
-        for (int k = 0; k < n_prob; ++k) hts[k] = trees[k]->host.get();
+        for (int k = 0; k < n_prob; ++k) hts[k] = &host_of(trees[k]);
         auto s = std::make_unique<EvalState>();
         s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1),
                                    g_m2l_split.load() != 0, pair_fill(n), max_pairs(n, 1)));

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "forest.hpp"
+#include "host_tree.hpp"
 #include "kifmm.h"
 
 namespace kifmm {
@@ -52,6 +53,34 @@ void evaluate_simple_host(EvalState& st, const HostOps& hops, OpsCache& oc, cons
 void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out);
 
 int current_device();
+
+// Device arrays of a single-tree forest that new point positions rewrite in
+// place (kifmm_tree_update_points); device -1 when no forest is resident.
+struct DevPointView {
+  int device = -1;
+  int32_t nbox = 0;
+  void* box_src = nullptr;  // int2 [nbox]: sorted point range of each box
+  void* box_tgt = nullptr;
+  void* src64 = nullptr;    // double4 [n]: leaf-frame coordinates
+  void* tgt64 = nullptr;
+  int32_t* src_perm = nullptr;  // [n]: sorted position -> caller index
+  int32_t* tgt_perm = nullptr;
+};
+DevPointView dev_point_view(const EvalState& st);
+
+// New point positions of a uniform tree, sorted on the device (see
+// tree_update.hip) and held there until the host copy of the tree is
+// refreshed from them.
+struct PendingPoints;
+// Sorts src (and tgt; null: the sources) into T's leaves on the device and,
+// if st has a forest resident on the current device, rewrites it in place.
+// Throws Error: EINVAL if a point falls in another leaf set than T's (T and
+// st unchanged), EUNSUPPORTED for a non-uniform tree.  Synchronises stream.
+PendingPoints* update_points_device(const HostTree& T, EvalState* st, const double* src, const double* tgt,
+                                    void* stream);
+// Copies the sorted order, coordinates, keys and box ranges into T.
+void pending_to_host(PendingPoints* p, HostTree& T);
+void pending_free(PendingPoints* p);
 
 // smallest order at which FP32-bulk modes evaluate L2P/M2P terms in FP64
 void set_far_fp64_min_p(int p);

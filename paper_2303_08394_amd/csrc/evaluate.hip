@@ -22,21 +22,9 @@
 
 #include "common.hpp"
 #include "device.hpp"
+#include "hip_check.hpp"
 
 namespace kifmm {
-
-#define HIPCHECK(expr)                                                                   \
-  do {                                                                                   \
-    hipError_t e_ = (expr);                                                              \
-    if (e_ != hipSuccess)                                                                \
-      raise(KIFMM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));           \
-  } while (0)
-
-#define LAUNCHCHECK(what)                                                                \
-  do {                                                                                   \
-    hipError_t e_ = hipGetLastError();                                                   \
-    if (e_ != hipSuccess) raise(KIFMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e_)); \
-  } while (0)
 
 static constexpr double kInv4Pi = 0.0795774715459476678844418816863;
 static constexpr double kRin = 1.05, kRout = 2.95;
@@ -136,6 +124,21 @@ struct DevForest {
 };
 
 EvalState::~EvalState() { delete forest; }
+
+DevPointView dev_point_view(const EvalState& st) {
+  DevPointView v;
+  const DevForest* F = st.forest;
+  if (!F || F->nprob != 1) return v;
+  v.device = st.device;
+  v.nbox = F->nbox;
+  v.box_src = F->box_src;
+  v.box_tgt = F->box_tgt;
+  v.src64 = F->src64;
+  v.tgt64 = F->tgt64;
+  v.src_perm = F->src_perm;
+  v.tgt_perm = F->tgt_perm;
+  return v;
+}
 OpsCache::~OpsCache() {
   for (auto& kv : per_device) delete kv.second;
 }

@@ -43,7 +43,8 @@ class TreeInfo(C.Structure):
 _lib = None
 EXPORTED = [
     "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
-    "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_precompute_operators",
+    "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
+    "kifmm_precompute_operators",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
@@ -65,6 +66,7 @@ def lib():
     L.kifmm_tree_export_boxes.argtypes = [P, P, P, P, P, P, P]
     L.kifmm_tree_export_list.argtypes = [P, I32, P, P]
     L.kifmm_tree_export_perm.argtypes = [P, P, P]
+    L.kifmm_tree_update_points.argtypes = [P, P, P, P]
     L.kifmm_precompute_operators.argtypes = [I32, C.c_double, C.POINTER(P)]
     L.kifmm_ops_export.argtypes = [P, I32, D, I64]
     L.kifmm_ops_n.argtypes = [P]
@@ -159,6 +161,19 @@ class Tree:
         s, t = np.zeros(inf.n_src, np.int64), np.zeros(inf.n_tgt, np.int64)
         _check(lib().kifmm_tree_export_perm(self._h, _vptr(s), _vptr(t)))
         return s, t
+
+    def update_points(self, src, tgt=None, stream=None):
+        """New positions of the points of a uniform tree, re-sorted on the GPU
+        (kifmm_tree_update_points).  src, tgt: float64 CUDA tensors [n][3];
+        tgt None if the tree's targets are its sources."""
+        import torch
+        for a in (src, tgt):
+            if a is not None and (not a.is_cuda or a.dtype != torch.float64 or a.dim() != 2
+                                  or a.shape[1] != 3 or not a.is_contiguous()):
+                raise ValueError("update_points: contiguous float64 CUDA tensors of shape [n, 3]")
+        _check(lib().kifmm_tree_update_points(self._h, C.c_void_p(src.data_ptr()),
+                                              None if tgt is None else C.c_void_p(tgt.data_ptr()),
+                                              _stream_ptr(stream)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
