@@ -1,7 +1,11 @@
 """O1: direct evaluation of the Laplace potential (Eq. 1, section "The Fast
-Multipole Method").
+Multipole Method"), and of its gradient at the targets.
 
     phi_j = sum_{i, x_i != x_j} q_i / (4 pi |x_i - x_j|)
+    grad phi_j = sum_{i, x_i != x_j} -q_i (x_j - x_i) / (4 pi |x_j - x_i|^3)
+
+(The gradient is the derivative of Eq. (1) in the target position; the paper
+evaluates potentials only, so it is an extension with a plain definition.)
 
 Self-interaction is excluded.  For general (distinct) source and target
 arrays the excluded pairs are exactly those at distance zero: a target that
@@ -47,4 +51,35 @@ def direct(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
     for s in range(0, len(tgt), chunk):
         k = kernel_matrix(tgt[s:s + chunk], src)
         out[:, s:s + chunk] = (k @ q2.T).T
+    return out[0] if one else out
+
+
+def gradient_matrices(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """G[c, i, j] = d/dx_c of 1 / (4 pi |x_i - y_j|) = -(x_i - y_j)_c / (4 pi |x_i - y_j|^3),
+    and 0 where x_i == y_j.  Returns (3, m, n) float64."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    d = x[None, :, :].transpose(2, 1, 0) - y[None, :, :].transpose(2, 0, 1)  # (3, m, n)
+    r2 = (d * d).sum(axis=0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        w = -INV_4PI / (r2 * np.sqrt(r2))
+    w[r2 == 0.0] = 0.0
+    return d * w[None]
+
+
+def direct_gradient(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
+                    chunk: int = 1024) -> np.ndarray:
+    """Gradients of the potential at tgt, by the O(N^2) sum (derivative of Eq. 1).
+
+    charges (n_src,) or (n_rhs, n_src).  Returns (3, n_tgt) or
+    (n_rhs, 3, n_tgt), matching the charges' rank.
+    """
+    q = np.asarray(charges, dtype=np.float64)
+    one = q.ndim == 1
+    q2 = q[None, :] if one else q
+    out = np.zeros((q2.shape[0], 3, len(tgt)))
+    for s in range(0, len(tgt), chunk):
+        g = gradient_matrices(tgt[s:s + chunk], src)
+        for c in range(3):
+            out[:, c, s:s + chunk] = (g[c] @ q2.T).T
     return out[0] if one else out

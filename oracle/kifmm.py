@@ -28,7 +28,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .direct import kernel_matrix
+from .direct import gradient_matrices, kernel_matrix
 from .octree import Octree
 from .surface import RADIUS_INNER, RADIUS_OUTER, surface_grid
 
@@ -121,14 +121,19 @@ class KIFMM:
         return tuple(t.anchor[b][d] - 2 * pa[d] for d in range(3))
 
     # -- evaluation ------------------------------------------------------------
-    def evaluate(self, charges, sample=None):
+    def evaluate(self, charges, sample=None, gradient=False):
         """Potentials at the tree's targets.
 
         charges: (n_src,) or (n_rhs, n_src) float64.
         sample: optional target indices; then only the leaves holding them
         (and their ancestors) run the downward pass, and only those targets
         are returned, in the order given.
-        Returns (n_tgt,) / (n_rhs, n_tgt), or (..., len(sample)).
+        gradient: also return the gradient of the potential at the targets:
+        the leaf stage (L2P, M2P, near field) applies the derivative of the
+        kernel in the target position to the same densities and charges.
+        Returns (n_tgt,) / (n_rhs, n_tgt), or (..., len(sample)); with
+        gradient, the pair (potentials, gradients of shape (3, n_tgt) /
+        (n_rhs, 3, n_tgt)).
         """
         t = self.tree
         q = np.asarray(charges, dtype=np.float64)
@@ -189,22 +194,36 @@ class KIFMM:
 
         # Leaves: L2P + M2P (W) + near field (U).
         pot = np.zeros((len(t.tgt), n_rhs))
+        grad = np.zeros((3, len(t.tgt), n_rhs)) if gradient else None
         for b in tleaves:
             ids = t.tgts[b]
             x = t.tgt[ids]
-            acc = np.zeros((len(ids), n_rhs))
+            terms = []  # (sources, densities) seen by the leaf's targets
             if b in down:
-                acc += kernel_matrix(x, self._surf(b, RADIUS_OUTER)) @ down[b]
+                terms.append((self._surf(b, RADIUS_OUTER), down[b]))
             for a in t.W(b):
-                acc += kernel_matrix(x, self._surf(a, RADIUS_INNER)) @ up[a]
+                terms.append((self._surf(a, RADIUS_INNER), up[a]))
             for a in t.U(b):
                 s_ids = t.srcs[a]
-                acc += kernel_matrix(x, t.src[s_ids]) @ qm[s_ids]
+                terms.append((t.src[s_ids], qm[s_ids]))
+            acc = np.zeros((len(ids), n_rhs))
+            for y, dens in terms:
+                acc += kernel_matrix(x, y) @ dens
             pot[ids] = acc
+            if gradient:
+                for y, dens in terms:
+                    g = gradient_matrices(x, y)
+                    for c in range(3):
+                        grad[c, ids] += g[c] @ dens
         out = pot.T
         if sample is not None:
             out = out[:, sample]
-        return out[0] if one else out
+        if not gradient:
+            return out[0] if one else out
+        gout = grad.transpose(2, 0, 1)  # (n_rhs, 3, n_tgt)
+        if sample is not None:
+            gout = gout[:, :, sample]
+        return (out[0], gout[0]) if one else (out, gout)
 
 
 def kifmm(src, charges, tgt, p, *, uniform_depth=-1, ncrit=64, max_depth=12,
