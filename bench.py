@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--no-fp64-leg", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="time eager launches instead of graph replays")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the potential + gradient leg")
     ap.add_argument("--direct-sample", type=int, default=200)
     ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128/192)")
     ap.add_argument("--m2l-pair-fill", type=int, default=-1,
@@ -336,6 +337,27 @@ def main():
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
     roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
+
+    if not batch and n_rhs == 1 and not args.no_gradient:
+        # potentials + gradients (kifmm_evaluate_gradient), graph replays as
+        # above, against the FP64 gradient on the same tree
+        def grad_run(prec, steps):
+            out = torch.empty((1, 4, n), dtype=torch.float64, device=dev)
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                for _ in range(2):
+                    K.evaluate_gradient(tree, ops, qs[0], precision=prec, out=out)
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                for _ in range(steps):
+                    K.evaluate_gradient(tree, ops, qs[0], precision=prec, out=out)
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+            return out.cpu().numpy()[0], (tb - ta) / steps
+        g, tg = grad_run(precision, args.steps)
+        g64, _ = grad_run("fp64", 1)
+        result["gradient"] = {"ms_per_step": tg * 1e3, "Mpoints_per_s": n / tg / 1e6,
+                              "rel_l2_vs_fp64_gpu": rel(g[1:], g64[1:])}
 
     if not batch and prob.uniform_depth >= 0 and prob.halfwidth > 0:
         # the tree's points re-sorted on the device after each point moves to

@@ -177,6 +177,19 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops,
                             int32_t io_fp64, kifmm_precision precision,
                             void* hip_stream);
 
+/* Potentials and their gradients at the targets (the derivative of Eq. (1)
+ * in the target position; the paper evaluates potentials only).  The
+ * multipole passes are those of kifmm_evaluate; the leaf stage (L2P, M2P,
+ * near field) also applies the kernel's derivative to the same densities and
+ * charges.  out: DEVICE [n_rhs][4][n_tgt] (caller order): component 0 the
+ * potential, 1..3 d/dx, d/dy, d/dz; FP64 if io_fp64 != 0, else FP32.  Other
+ * arguments, stream semantics and errors as kifmm_evaluate.  The potential
+ * component equals kifmm_evaluate's result to rounding. */
+kifmm_status kifmm_evaluate_gradient(const kifmm_tree* tree, const kifmm_ops* ops,
+                                     const void* charges, int32_t n_rhs, void* out,
+                                     int32_t io_fp64, kifmm_precision precision,
+                                     void* hip_stream);
+
 /* Evaluate n_prob independent problems (each its own tree, n_rhs = 1) in one
  * pass: every operator runs as one launch over all problems.  charges[k],
  * potentials[k]: device buffers of problem k, as in kifmm_evaluate.  The

@@ -259,9 +259,11 @@ kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out, 
   return KIFMM_OK;
 }
 
-kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const void* charges,
-                            int32_t n_rhs, void* potentials, int32_t io_fp64,
-                            kifmm_precision precision, void* hip_stream) {
+}  // extern "C"
+
+static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, const void* charges,
+                                  int32_t n_rhs, void* potentials, int32_t io_fp64,
+                                  kifmm_precision precision, void* hip_stream, bool grad) {
   return guard([&] {
     check_eval_args(tree, ops, n_rhs, precision);
     if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate: null charges or potentials");
@@ -285,8 +287,23 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
     const void* q[1] = {charges};
     void* o[1] = {potentials};
     evaluate_forest(*t->state, *ops->host, const_cast<kifmm_ops*>(ops)->cache, q, o, n_rhs,
-                    io_fp64 != 0, precision, hip_stream);
+                    io_fp64 != 0, precision, hip_stream, grad);
   });
+}
+
+extern "C" {
+
+kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const void* charges,
+                            int32_t n_rhs, void* potentials, int32_t io_fp64,
+                            kifmm_precision precision, void* hip_stream) {
+  return evaluate_impl(tree, ops, charges, n_rhs, potentials, io_fp64, precision, hip_stream, false);
+}
+
+kifmm_status kifmm_evaluate_gradient(const kifmm_tree* tree, const kifmm_ops* ops,
+                                     const void* charges, int32_t n_rhs, void* out,
+                                     int32_t io_fp64, kifmm_precision precision,
+                                     void* hip_stream) {
+  return evaluate_impl(tree, ops, charges, n_rhs, out, io_fp64, precision, hip_stream, true);
 }
 
 kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees,

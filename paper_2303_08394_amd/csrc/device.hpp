@@ -40,9 +40,11 @@ struct OpsCache {
 };
 
 // Runs the evaluation; throws kifmm::Error.
+// With grad, potentials[k] holds [n_rhs][4][n_tgt]: the potential and its
+// gradient (d/dx, d/dy, d/dz) at every target.
 void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& ocache,
                      const void* const* charges, void* const* potentials, int n_rhs,
-                     bool io_fp64, kifmm_precision prec, void* stream);
+                     bool io_fp64, kifmm_precision prec, void* stream, bool grad = false);
 
 // Host-memory convenience: copies charges in, evaluates in FP32 with FP64
 // input/output on the default stream, copies potentials out, synchronously.

@@ -381,8 +381,9 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
   return O;
 }
 
-static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
-  DevWork*& W = F.work[{fp64 ? 1 : 0, n_rhs}];
+static DevWork* work_for(DevForest& F, bool fp64, int n_rhs, bool grad = false) {
+  // (buffers of gradient evaluations are kept apart: 4 values per target)
+  DevWork*& W = F.work[{(fp64 ? 1 : 0) | (grad ? 2 : 0), n_rhs}];
   if (W) return W;
   W = new DevWork();
   W->n_rhs = n_rhs;
@@ -401,7 +402,7 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs) {
   W->up_eq = alloc_bytes(W->col_bytes);
   W->dn_chk = alloc_bytes(W->col_bytes);
   W->dn_eq = alloc_bytes(W->col_bytes);
-  W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * F.ntgt * 8));
+  W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * (grad ? 4 : 1) * F.ntgt * 8));
   W->absmax = static_cast<unsigned*>(alloc_bytes(16));
   return W;
 }
@@ -697,6 +698,7 @@ struct P2PArgs {
   const int32_t* l1_items;
   const int32_t* l2_off;
   const int32_t* l2_items;
+  int grad;  // leaf kernel: also the gradient (pot holds [n_rhs][4][ntgt])
 };
 
 template <class T, int RC>
@@ -764,12 +766,14 @@ __device__ inline void segment_info(const P2PArgs<T>& a, int wi, int B, int4 gB,
 }
 
 // Accumulates the sources of segments [s0, s1) into acc, computing pair terms
-// in precision U (staging in LDS, FP32/FP64 partials folded into FP64).
-template <class U, class T, int MODE, int RC, int TCH>
+// in precision U (staging in LDS, FP32/FP64 partials folded into FP64).  With
+// GRAD (one right-hand side), gacc also sums q (x - y) / |x - y|^3 per axis.
+template <class U, class T, int MODE, int RC, int TCH, bool GRAD = false>
 __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st, int wi, int B,
                           int4 gB, int nU, int s0, int s1, int rhs0, const double (&tx)[kNch],
                           const double (&ty)[kNch], const double (&tz)[kNch], int nchunks,
-                          double (&acc)[kNch][RC]) {
+                          double (&acc)[kNch][RC], double (&gacc)[kNch][3]) {
+  static_assert(!GRAD || RC == 1, "gradients are summed for one right-hand side per block");
   using C = P2PCfg<U, RC>;
   using V = typename V4<U>::type;
   constexpr int NT = 256, SL = NT / TCH, CAP = C::CAP;
@@ -872,7 +876,7 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 #pragma unroll
       for (int c = 0; c < kNch; ++c) {
         if (c < nchunks) {
-          U part[RC];
+          U part[RC], gpart[3] = {U(0), U(0), U(0)};
 #pragma unroll
           for (int r = 0; r < RC; ++r) part[r] = U(0);
           const U x = ux[c], y = uy[c], z = uz[c];
@@ -886,6 +890,12 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
             else ri = rinv_nonzero(r2);
             if constexpr (RC == 1) {
               part[0] += s.w * ri;
+              if constexpr (GRAD) {
+                const U qr3 = s.w * ri * ri * ri;
+                gpart[0] += qr3 * dx;
+                gpart[1] += qr3 * dy;
+                gpart[2] += qr3 * dz;
+              }
             } else {
 #pragma unroll
               for (int r = 0; r < RC; ++r) part[r] += s_q[r * CAP + j] * ri;
@@ -929,6 +939,10 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
           }
 #pragma unroll
           for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
+          if constexpr (GRAD) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) gacc[c][k] += double(gpart[k]);
+          }
         }
       }
       __syncthreads();
@@ -945,12 +959,14 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 // groups stride over the staged sources, then reduce in FP64.  Particle
 // segments are computed in T, equivalent-surface segments (L2P, M2P) in TF:
 // FP64 at high order, where the equivalent densities cancel strongly.
-template <class T, class TF, int MODE, int RC, int TCH>
+template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
   constexpr int NT = 256, SL = NT / TCH;
+  static_assert(!GRAD || (MODE == MODE_LEAF && RC == 1), "gradients: leaf kernel, one right-hand side");
   constexpr int SMEM0 = P2PCfg<T, RC>::BYTES > P2PCfg<TF, RC>::BYTES ? P2PCfg<T, RC>::BYTES
                                                                      : P2PCfg<TF, RC>::BYTES;
-  constexpr int RED = NT * RC * 8;
+  constexpr int NV = RC + (GRAD ? 3 : 0);  // reduced values per target
+  constexpr int RED = NT * NV * 8;
   __shared__ __align__(16) unsigned char smem[SMEM0 > RED ? SMEM0 : RED];
   __shared__ SegTable st;
   double* s_red = reinterpret_cast<double*>(smem);
@@ -987,7 +1003,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 
   for (int t0 = 0; t0 < nt; t0 += TCH * kNch) {
     double tx[kNch], ty[kNch], tz[kNch];
-    double acc[kNch][RC];
+    double acc[kNch][RC], gacc[kNch][3];
 #pragma unroll
     for (int c = 0; c < kNch; ++c) {
       int t = t0 + c * TCH + ti;
@@ -1007,12 +1023,16 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       }
 #pragma unroll
       for (int r = 0; r < RC; ++r) acc[c][r] = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) gacc[c][k] = 0.0;
     }
     const int nchunks = (min(nt - t0, TCH * kNch) + TCH - 1) / TCH;
     if (MODE != MODE_FAR)
-      p2p_phase<T, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks, acc);
+      p2p_phase<T, T, MODE, RC, TCH, GRAD>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks,
+                                           acc, gacc);
     if (MODE != MODE_NEAR && nseg > nnear)
-      p2p_phase<TF, T, MODE, RC, TCH>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz, nchunks, acc);
+      p2p_phase<TF, T, MODE, RC, TCH, GRAD>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz,
+                                            nchunks, acc, gacc);
 
     // reduce the slices of each chunk and write
     const double rB = a.box_r[B];
@@ -1021,15 +1041,37 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       if (c < nchunks) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RC; ++r) s_red[(sl * TCH + ti) * RC + r] = acc[c][r];
+        for (int r = 0; r < RC; ++r) s_red[(sl * TCH + ti) * NV + r] = acc[c][r];
+        if constexpr (GRAD) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k) s_red[(sl * TCH + ti) * NV + 1 + k] = gacc[c][k];
+        }
         __syncthreads();
         if (sl == 0) {
           const int t = t0 + c * TCH + ti;
           if (t < nt) {
+            if constexpr (GRAD) {
+              // potentials then gradients: component k of right-hand side
+              // rr at pot[(4 rr + k) ntgt + target]; the frame's unit is r_B,
+              // so d/dx = (1 / r_B) d/dx~, and d/dx~ 1/|x~ - y~| = -(x~ - y~) / |x~ - y~|^3
+              const int rr = rhs0;
+              if (rr < a.n_rhs) {
+                double v[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  v[k] = 0.0;
+                  for (int s2 = 0; s2 < SL; ++s2) v[k] += s_red[(s2 * TCH + ti) * NV + k];
+                }
+                double* o = a.pot + int64_t(4 * rr) * a.ntgt + tbase + t;
+                o[0] = v[0] * (kInv4Pi / rB);
+#pragma unroll
+                for (int k = 1; k < 4; ++k) o[int64_t(k) * a.ntgt] = -v[k] * (kInv4Pi / (rB * rB));
+              }
+            } else {
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
               double sum = 0.0;
-              for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * TCH + ti) * RC + r];
+              for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * TCH + ti) * NV + r];
               const int rr = rhs0 + r;
               if (rr < a.n_rhs) {
                 if (MODE == MODE_LEAF || MODE == MODE_NEAR) {
@@ -1042,6 +1084,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
                   else *o += T(sum * kInv4Pi);
                 }
               }
+            }
             }
           }
         }
@@ -1685,11 +1728,11 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   ps.launches++;
 }
 
-template <class T, class TF, int MODE, int RC, int TCH>
+template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false>
 static void run_p2p(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
   if (nwork == 0) return;
   dim3 grid(nwork, (n_rhs + RC - 1) / RC);
-  hipLaunchKernelGGL((p2p_kernel<T, TF, MODE, RC, TCH>), grid, dim3(256), 0, s, args);
+  hipLaunchKernelGGL((p2p_kernel<T, TF, MODE, RC, TCH, GRAD>), grid, dim3(256), 0, s, args);
   LAUNCHCHECK("p2p_kernel");
   ps.launches++;
 }
@@ -1704,6 +1747,14 @@ void set_far_fp64_min_p(int p) { g_far_fp64_min_p = p; }
 template <class T, int MODE, int TCH>
 static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64, hipStream_t s,
                        PhaseScope& ps) {
+  if constexpr (MODE == MODE_LEAF) {
+    if (args.grad) {
+      // potential and gradient: one right-hand side per block
+      if (far64) run_p2p<T, double, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
+      else run_p2p<T, T, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
+      return;
+    }
+  }
   if (far64) {
     if (n_rhs == 1) run_p2p<T, double, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
     else run_p2p<T, double, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
@@ -1744,7 +1795,7 @@ static Aux& aux_for(int dev) {
 template <class T, class TIO>
 static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* charges,
                      void* const* potentials, int n_rhs, kifmm_precision prec, bool check_form,
-                     hipStream_t s) {
+                     bool grad, hipStream_t s) {
   constexpr int GF = sizeof(T) == 8 ? GM_F64 : GM_F32;
   const int ld = F.ld;
   Aux& aux = aux_for(current_device());
@@ -1794,11 +1845,14 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.dn_eq = dn_eq;
   base.pot = W.pot;
   base.ntgt = F.ntgt;
+  base.grad = grad ? 1 : 0;
   // The near field needs only the gathered charges; it runs on the
   // auxiliary stream, forked after the gather (g_near_fork 0), after P2M (2),
   // before M2L (1) or after it (3), and is joined before the far field.  With
   // g_near_fork 4 near and far field run as one kernel at the end.
-  const bool merged_leaf = g_near_fork == 4;
+  // (gradients always take the merged leaf kernel)
+  const int near_fork = grad ? 4 : g_near_fork;
+  const bool merged_leaf = near_fork == 4;
   auto fork_near = [&]() {
     HIPCHECK(hipEventRecord(aux.forked, s));
     HIPCHECK(hipStreamWaitEvent(aux.stream, aux.forked, 0));
@@ -1815,7 +1869,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     }
     HIPCHECK(hipEventRecord(aux.joined, aux.stream));
   };
-  if (g_near_fork == 0) fork_near();
+  if (near_fork == 0) fork_near();
   {
     PhaseScope ps(PH_P2M, s);
     P2PArgs<T> a = base;
@@ -1823,7 +1877,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.out_col = up_chk;
     run_p2p_rc<T, MODE_P2M, 64>(a, F.n_p2m, n_rhs, false, s, ps);
   }
-  if (g_near_fork == 2) fork_near();
+  if (near_fork == 2) fork_near();
   for (int l = F.depth; l >= 2; --l) {
     {
       PhaseScope ps(PH_M2M, s);
@@ -1846,7 +1900,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, 0, ld, F.nbox, n_rhs, up_chk, up_eq, false, s, ps);
     }
   }
-  if (g_near_fork == 1) fork_near();
+  if (near_fork == 1) fork_near();
   {
     // operand of M2L: upward densities, or (check form) upward check potentials
     const T* m2l_in = check_form ? up_chk : up_eq;
@@ -1945,7 +1999,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       ps.launches++;
     }
   }
-  if (g_near_fork == 3) fork_near();
+  if (near_fork == 3) fork_near();
   {
     PhaseScope ps(PH_P2L, s);
     P2PArgs<T> a = base;
@@ -1987,8 +2041,9 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       PtrPack pk{};
       for (int k = 0; k < nk; ++k) pk.p[k] = potentials[k0 + k];
       dim3 grid(unsigned((F.max_tgt_per_prob + 255) / 256), nk);
+      // (gradients: 4 columns per right-hand side, potential then d/dx, d/dy, d/dz)
       hipLaunchKernelGGL((scatter_kernel<TIO>), grid, dim3(256), 0, s, pk, k0, F.tgt_off,
-                         F.tgt_perm, n_rhs, F.ntgt, W.pot);
+                         F.tgt_perm, n_rhs * (grad ? 4 : 1), F.ntgt, W.pot);
       LAUNCHCHECK("scatter_kernel");
       ps.launches++;
     }
@@ -2002,7 +2057,7 @@ void set_use_graphs(bool on) { g_use_graphs = on; }
 
 void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const void* const* charges,
                      void* const* potentials, int n_rhs, bool io_fp64, kifmm_precision prec,
-                     void* stream) {
+                     void* stream, bool grad) {
   const int dev = current_device();
   if (!st.forest || st.device != dev) {
     delete st.forest;
@@ -2022,17 +2077,17 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   DevOps* O = ops_for_device(oc, hops, dev, need);
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
-  DevWork* W = work_for(F, fp64, n_rhs);
+  DevWork* W = work_for(F, fp64, n_rhs, grad);
   if (need.bf16 || need.f16) ensure_split(F, W);
   ensure_pairs(F, W);
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto launch_all = [&]() {
     if (fp64) {
-      if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
-      else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+      if (io_fp64) pipeline<double, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, grad, s);
+      else pipeline<double, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, grad, s);
     } else {
-      if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
-      else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, s);
+      if (io_fp64) pipeline<float, double>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, grad, s);
+      else pipeline<float, float>(F, *O, *W, charges, potentials, n_rhs, prec, need.check_form, grad, s);
     }
   };
   if (!g_use_graphs || g_prof.on || s == nullptr) {
@@ -2046,7 +2101,8 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
                                   reinterpret_cast<const void*>(intptr_t(g_far_fp64_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_check_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p)),
-                                  reinterpret_cast<const void*>(intptr_t(g_near_fork))};
+                                  reinterpret_cast<const void*>(intptr_t(g_near_fork)),
+                                  reinterpret_cast<const void*>(intptr_t(grad))};
   for (int k = 0; k < F.nprob; ++k) {
     key.push_back(charges[k]);
     key.push_back(potentials[k]);
@@ -2118,7 +2174,7 @@ void evaluate_simple_host(EvalState& st, const HostOps& hops, OpsCache& oc, cons
   HIPCHECK(hipMemcpy(dq, q, size_t(nsrc) * 8, hipMemcpyHostToDevice));
   const void* qa[1] = {dq};
   void* pa[1] = {dp};
-  evaluate_forest(st, hops, oc, qa, pa, 1, true, KIFMM_FP32, nullptr);
+  evaluate_forest(st, hops, oc, qa, pa, 1, true, KIFMM_FP32, nullptr, false);
   HIPCHECK(hipStreamSynchronize(nullptr));
   HIPCHECK(hipMemcpy(pot, dp, size_t(ntgt) * 8, hipMemcpyDeviceToHost));
 }

@@ -45,7 +45,7 @@ EXPORTED = [
     "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
     "kifmm_precompute_operators",
-    "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_batch",
+    "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
@@ -72,6 +72,7 @@ def lib():
     L.kifmm_ops_n.argtypes = [P]
     L.kifmm_ops_n.restype = I32
     L.kifmm_evaluate.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
+    L.kifmm_evaluate_gradient.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
     L.kifmm_evaluate_batch.argtypes = [I32, C.POINTER(P), P, C.POINTER(P), C.POINTER(P), I32,
                                        C.c_int, P]
     L.kifmm_evaluate_simple.argtypes = [D, D, I64, D, I64, I32, D]
@@ -238,10 +239,43 @@ def evaluate(tree: Tree, ops: Operators, charges, precision="fp32", out=None, st
     n_rhs = q.shape[0]
     if out is None:
         out = torch.empty((n_rhs, inf.n_tgt), dtype=q.dtype, device=q.device)
+    _check_out(out, n_rhs * inf.n_tgt, q)
     _check(lib().kifmm_evaluate(tree.handle, ops.handle, C.c_void_p(q.data_ptr()), n_rhs,
                                 C.c_void_p(out.data_ptr()), 1 if q.dtype == torch.float64 else 0,
                                 prec, _stream_ptr(stream)))
-    return out[0] if one else out
+    return out.reshape(inf.n_tgt) if one else out.reshape(n_rhs, inf.n_tgt)
+
+
+def _check_out(out, numel, q):
+    if (not out.is_cuda or out.dtype != q.dtype or not out.is_contiguous()
+            or out.numel() != numel or out.device != q.device):
+        raise ValueError(f"out must be a contiguous {q.dtype} tensor of {numel} elements on {q.device}")
+
+
+def evaluate_gradient(tree: Tree, ops: Operators, charges, precision="fp32", out=None, stream=None):
+    """Potentials and gradients at the tree's targets (kifmm_evaluate_gradient).
+
+    charges: torch CUDA tensor [n_rhs][n_src] (or [n_src]), float64 or float32.
+    Returns [n_rhs][4][n_tgt] (or [4][n_tgt]): potential, d/dx, d/dy, d/dz."""
+    import torch
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if not charges.is_cuda:
+        raise ValueError("charges must be a CUDA (HIP) tensor")
+    one = charges.dim() == 1
+    q = (charges.reshape(1, -1) if one else charges).contiguous()
+    if q.dtype not in (torch.float64, torch.float32):
+        raise ValueError("charges must be float64 or float32")
+    inf = tree.info()
+    if q.shape[1] != inf.n_src:
+        raise ValueError(f"charges have {q.shape[1]} columns, the tree {inf.n_src} sources")
+    n_rhs = q.shape[0]
+    if out is None:
+        out = torch.empty((n_rhs, 4, inf.n_tgt), dtype=q.dtype, device=q.device)
+    _check_out(out, n_rhs * 4 * inf.n_tgt, q)
+    _check(lib().kifmm_evaluate_gradient(tree.handle, ops.handle, C.c_void_p(q.data_ptr()), n_rhs,
+                                         C.c_void_p(out.data_ptr()), 1 if q.dtype == torch.float64 else 0,
+                                         prec, _stream_ptr(stream)))
+    return out.reshape(4, inf.n_tgt) if one else out.reshape(n_rhs, 4, inf.n_tgt)
 
 
 def evaluate_batch(trees, ops: Operators, charges, precision="fp32", outs=None, stream=None):
@@ -251,8 +285,17 @@ def evaluate_batch(trees, ops: Operators, charges, precision="fp32", outs=None, 
     n = len(trees)
     qs = [c.contiguous() for c in charges]
     dt = qs[0].dtype
+    if len(qs) != n:
+        raise ValueError("one charge vector per tree")
+    for t, q in zip(trees, qs):
+        if not q.is_cuda or q.dtype != dt or q.numel() != t.info().n_src:
+            raise ValueError("charges: one CUDA vector per tree, of its source count and one dtype")
     if outs is None:
         outs = [torch.empty(t.info().n_tgt, dtype=dt, device=qs[0].device) for t in trees]
+    if len(outs) != n:
+        raise ValueError("one output per tree")
+    for t, o, q in zip(trees, outs, qs):
+        _check_out(o, t.info().n_tgt, q)
     th = (C.c_void_p * n)(*[t.handle.value for t in trees])
     qp = (C.c_void_p * n)(*[q.data_ptr() for q in qs])
     op = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
