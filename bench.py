@@ -192,7 +192,10 @@ def main():
                     center=p.center, halfwidth=p.halfwidth) for p in probs]
     t_tree = time.perf_counter() - t0
     t0 = time.perf_counter()
-    ops = K.Operators(prob.p)
+    # the pseudo-inverses on the GPU from p = 8 on (their host SVD dominates
+    # there: 7 s at p = 10); below, the host is as fast
+    ops_on_gpu = prob.p >= 8
+    ops = K.Operators(prob.p, device_svd=ops_on_gpu)
     t_ops = time.perf_counter() - t0
     tree = trees[0]
     info = tree.info()
@@ -402,6 +405,7 @@ def main():
         "work": {"m2l_flop": flops_m2l, "v_pairs": v_pairs, "near_pairs": near_pairs,
                  "leaf_far_pairs": far_pairs},
         "tree_build_s": t_tree,
+        "precompute_svd": "gpu" if ops_on_gpu else "host",
         "precompute_s": t_ops,
         **result,
     }

@@ -156,6 +156,26 @@ kifmm_status kifmm_tree_update_points(kifmm_tree* tree, const double* src_xyz,
  * The device copy is made on first use. */
 kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out);
 
+/* kifmm_precompute_operators with options.  flags: 0, or
+ * KIFMM_PRECOMPUTE_DEVICE_SVD: the two check-to-equivalent pseudo-inverses
+ * (the dominant cost: an n x n SVD each, n = 488 at p = 10) are computed on
+ * the current GPU with rocSOLVER's FP64 SVD and the same truncation rule;
+ * they agree with the host's one-sided Jacobi result to the conditioning of
+ * the kept singular values (~1e-9 relative), not bitwise.  Synchronises the
+ * device.  EINVAL for an unknown flag; EDEVICE if the GPU SVD fails. */
+#define KIFMM_PRECOMPUTE_DEVICE_SVD 1
+kifmm_status kifmm_precompute_operators_ex(int32_t p, double rcond, int32_t flags,
+                                           kifmm_ops** out);
+
+/* Persistent operator cache.  kifmm_ops_save writes every table of `ops`
+ * with its key (p, rcond, the surface radii 1.05 / 2.95) and a checksum to
+ * `path` (through a temporary file renamed into place).  kifmm_ops_load
+ * reads it back, bitwise equal, if the file holds operators of exactly
+ * (p, rcond) and is intact; otherwise EINVAL with the reason (missing,
+ * foreign or damaged file, other key), and *out is untouched. */
+kifmm_status kifmm_ops_save(const kifmm_ops* ops, const char* path);
+kifmm_status kifmm_ops_load(const char* path, int32_t p, double rcond, kifmm_ops** out);
+
 /* Copy an operator table out (tests): which = 0 surface [n][3], 1 UC2E [n][n],
  * 2 DC2E [n][n], 3 M2M [8][n][n], 4 L2L [8][n][n], 5 M2L [316][n][n],
  * 6 M2L offsets [316][3] (as doubles).  Row-major, reference box of

@@ -17,7 +17,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkifmm.so")
 
 HOST_SOURCES = ["host_tree.cpp", "precompute.cpp", "forest.cpp", "api.cpp"]
-HIP_SOURCES = ["evaluate.hip", "tree_update.hip"]
+HIP_SOURCES = ["evaluate.hip", "tree_update.hip", "precompute_device.hip"]
 ARCH = "gfx950"
 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-Wall",
@@ -57,7 +57,8 @@ def build(verbose: bool = False) -> str:
                 print(out)
     objs = [j[-1] for j in jobs]
     tmp = LIB + ".tmp"
-    _run([_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-pthread"])
+    _run([_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs, "-pthread",
+          "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -234,6 +234,31 @@ kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out
   });
 }
 
+kifmm_status kifmm_precompute_operators_ex(int32_t p, double rcond, int32_t flags, kifmm_ops** out) {
+  if (!out) return fail(KIFMM_EINVAL, "precompute_operators_ex: null output handle");
+  if (flags & ~int32_t(KIFMM_PRECOMPUTE_DEVICE_SVD))
+    return fail(KIFMM_EINVAL, "precompute_operators_ex: unknown flag");
+  return guard([&] {
+    auto o = std::make_unique<kifmm_ops>();
+    o->host.reset(build_host_ops(p, rcond, (flags & KIFMM_PRECOMPUTE_DEVICE_SVD) != 0));
+    *out = o.release();
+  });
+}
+
+kifmm_status kifmm_ops_save(const kifmm_ops* ops, const char* path) {
+  if (!ops) return fail(KIFMM_EINVAL, "ops_save: null ops");
+  return guard([&] { save_host_ops(*ops->host, path); });
+}
+
+kifmm_status kifmm_ops_load(const char* path, int32_t p, double rcond, kifmm_ops** out) {
+  if (!out) return fail(KIFMM_EINVAL, "ops_load: null output handle");
+  return guard([&] {
+    auto o = std::make_unique<kifmm_ops>();
+    o->host.reset(load_host_ops(path, p, rcond));
+    *out = o.release();
+  });
+}
+
 int32_t kifmm_ops_n(const kifmm_ops* ops) { return ops ? ops->host->n : -1; }
 
 kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out, int64_t n_out) {

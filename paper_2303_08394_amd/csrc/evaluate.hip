@@ -360,7 +360,7 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
     O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
   if (need.check_form) {
     if ((need.f16 && !O->m2lc_h) || (need.m2l32 && !O->m2lc32)) {
-      std::vector<double> pad = pad_table<double>(m2l_check_form(H), kNumM2L, H.n, O->ld);
+      std::vector<double> pad = pad_table<double>(m2l_check_form_device(H), kNumM2L, H.n, O->ld);
       if (need.f16 && !O->m2lc_h) O->m2lc_h = upload_split16(O, pad);
       if (need.m2l32 && !O->m2lc32) {
         std::vector<float> f(pad.begin(), pad.end());

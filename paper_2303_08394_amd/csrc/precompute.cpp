@@ -4,7 +4,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
 #include <numeric>
+#include <string>
 
 #include "common.hpp"
 
@@ -130,27 +134,7 @@ std::vector<double> pinv_truncated(const double* a, int n, double rcond, int* ra
   return P;
 }
 
-std::vector<double> m2l_check_form(const HostOps& O) {
-  const int n = O.n;
-  const size_t nn = size_t(n) * n;
-  std::vector<double> out(size_t(kNumM2L) * nn, 0.0);
-  parallel_for(kNumM2L, [&](int64_t b, int64_t e) {
-    for (int64_t k = b; k < e; ++k) {
-      const double* A = &O.m2l[size_t(k) * nn];
-      double* C = &out[size_t(k) * nn];
-      for (int i = 0; i < n; ++i)
-        for (int l = 0; l < n; ++l) {
-          const double a = A[size_t(i) * n + l];
-          const double* Br = &O.uc2e[size_t(l) * n];
-          double* Cr = &C[size_t(i) * n];
-          for (int j = 0; j < n; ++j) Cr[j] += a * Br[j];
-        }
-    }
-  }, 1);
-  return out;
-}
-
-HostOps* build_host_ops(int p, double rcond) {
+HostOps* build_host_ops(int p, double rcond, bool device_svd) {
   if (p < 2 || p > 16) raise(KIFMM_EINVAL, "precompute_operators: p must be in [2, 16]");
   if (!(rcond > 0.0 && rcond < 1.0)) raise(KIFMM_EINVAL, "precompute_operators: rcond must be in (0, 1)");
   auto* O = new HostOps();
@@ -164,10 +148,14 @@ HostOps* build_host_ops(int p, double rcond) {
     std::vector<double> k(nn);
     // UC2E: upward check (outer) <- upward equivalent (inner)
     kernel_block(O->surf, n, zero, kRadiusOuter, zero, kRadiusInner, k.data());
-    O->uc2e = pinv_truncated(k.data(), n, rcond);
+    O->device_svd = device_svd;
+    auto pinv = [&](const double* a) {
+      return device_svd ? pinv_truncated_device(a, n, rcond) : pinv_truncated(a, n, rcond);
+    };
+    O->uc2e = pinv(k.data());
     // DC2E: downward check (inner) <- downward equivalent (outer)
     kernel_block(O->surf, n, zero, kRadiusInner, zero, kRadiusOuter, k.data());
-    O->dc2e = pinv_truncated(k.data(), n, rcond);
+    O->dc2e = pinv(k.data());
     O->m2m.resize(8 * nn);
     O->l2l.resize(8 * nn);
     for (int o = 0; o < 8; ++o) {
@@ -199,6 +187,129 @@ HostOps* build_host_ops(int p, double rcond) {
     throw;
   }
   return O;
+}
+
+// --- persistent cache ------------------------------------------------------
+// Layout (little-endian): "KIFMMOPS", u32 version, i32 p, i32 n, f64 rcond,
+// f64 inner radius, f64 outer radius, i32 number of M2L offsets, u32 flags
+// (bit 0: GPU SVD), then surf, uc2e, dc2e, m2m, l2l, m2l (f64), m2l_offset
+// and m2l_index (i32), then the FNV-1a 64 hash of all preceding bytes.
+namespace {
+
+constexpr char kMagic[8] = {'K', 'I', 'F', 'M', 'M', 'O', 'P', 'S'};
+constexpr uint32_t kVersion = 1;
+
+struct Fnv {
+  uint64_t h = 1469598103934665603ULL;
+  void add(const void* p, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ULL;
+    }
+  }
+};
+
+}  // namespace
+
+void save_host_ops(const HostOps& O, const char* path) {
+  if (!path) raise(KIFMM_EINVAL, "ops_save: null path");
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) raise(KIFMM_EINVAL, std::string("ops_save: cannot write ") + tmp);
+  Fnv h;
+  bool ok = true;
+  auto put = [&](const void* p, size_t n) {
+    if (n == 0) return;
+    h.add(p, n);
+    ok = ok && std::fwrite(p, 1, n, f) == n;
+  };
+  const uint32_t version = kVersion, flags = O.device_svd ? 1u : 0u;
+  const int32_t p = O.p, n = O.n, nm2l = kNumM2L;
+  const double rin = kRadiusInner, rout = kRadiusOuter;
+  put(kMagic, 8);
+  put(&version, 4);
+  put(&p, 4);
+  put(&n, 4);
+  put(&O.rcond, 8);
+  put(&rin, 8);
+  put(&rout, 8);
+  put(&nm2l, 4);
+  put(&flags, 4);
+  for (const std::vector<double>* v : {&O.surf, &O.uc2e, &O.dc2e, &O.m2m, &O.l2l, &O.m2l})
+    put(v->data(), v->size() * 8);
+  put(O.m2l_offset.data(), O.m2l_offset.size() * 4);
+  put(O.m2l_index, sizeof(O.m2l_index));
+  const uint64_t sum = h.h;
+  ok = ok && std::fwrite(&sum, 1, 8, f) == 8;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    raise(KIFMM_EINVAL, std::string("ops_save: writing ") + path + " failed");
+  }
+}
+
+HostOps* load_host_ops(const char* path, int p, double rcond) {
+  if (!path) raise(KIFMM_EINVAL, "ops_load: null path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) raise(KIFMM_EINVAL, std::string("ops_load: cannot read ") + path);
+  std::unique_ptr<HostOps> O(new HostOps());
+  Fnv h;
+  bool ok = true;
+  auto get = [&](void* q, size_t n) {
+    if (n == 0 || !ok) return;
+    ok = std::fread(q, 1, n, f) == n;
+    if (ok) h.add(q, n);
+  };
+  auto bad = [&](const std::string& why) {
+    std::fclose(f);
+    raise(KIFMM_EINVAL, std::string("ops_load: ") + path + ": " + why);
+  };
+  char magic[8];
+  uint32_t version = 0, flags = 0;
+  int32_t fp = 0, fn = 0, nm2l = 0;
+  double frcond = 0, rin = 0, rout = 0;
+  get(magic, 8);
+  if (!ok || std::memcmp(magic, kMagic, 8) != 0) bad("not an operator cache file");
+  get(&version, 4);
+  if (!ok || version != kVersion) bad("unknown format version");
+  get(&fp, 4);
+  get(&fn, 4);
+  get(&frcond, 8);
+  get(&rin, 8);
+  get(&rout, 8);
+  get(&nm2l, 4);
+  get(&flags, 4);
+  if (!ok) bad("truncated header");
+  if (fp != p || frcond != rcond || rin != kRadiusInner || rout != kRadiusOuter || nm2l != kNumM2L)
+    bad("holds operators of another key (p, rcond or surface radii)");
+  const int n = p * p * p - (p - 2) * (p - 2) * (p - 2);
+  if (fn != n) bad("surface size does not match p");
+  O->p = p;
+  O->n = n;
+  O->rcond = rcond;
+  O->device_svd = (flags & 1u) != 0;
+  const size_t nn = size_t(n) * n;
+  O->surf.resize(3 * size_t(n));
+  O->uc2e.resize(nn);
+  O->dc2e.resize(nn);
+  O->m2m.resize(8 * nn);
+  O->l2l.resize(8 * nn);
+  O->m2l.resize(size_t(kNumM2L) * nn);
+  O->m2l_offset.resize(3 * size_t(kNumM2L));
+  for (std::vector<double>* v : {&O->surf, &O->uc2e, &O->dc2e, &O->m2m, &O->l2l, &O->m2l})
+    get(v->data(), v->size() * 8);
+  get(O->m2l_offset.data(), O->m2l_offset.size() * 4);
+  get(O->m2l_index, sizeof(O->m2l_index));
+  uint64_t sum = 0;
+  const uint64_t want = h.h;
+  if (ok) ok = std::fread(&sum, 1, 8, f) == 8;
+  if (!ok) bad("truncated");
+  char extra;
+  if (std::fread(&extra, 1, 1, f) != 0) bad("trailing bytes");
+  if (sum != want) bad("checksum mismatch (damaged file)");
+  std::fclose(f);
+  return O.release();
 }
 
 }  // namespace kifmm

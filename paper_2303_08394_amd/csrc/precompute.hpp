@@ -28,14 +28,30 @@ struct HostOps {
   std::vector<double> uc2e, dc2e, m2m, l2l, m2l;
   std::vector<int32_t> m2l_offset;  // [316][3] source anchor - target anchor
   int32_t m2l_index[343];           // (dx+3)*49 + (dy+3)*7 + (dz+3) -> op, or -1
+  bool device_svd = false;          // pseudo-inverses from the GPU SVD
 };
 
-HostOps* build_host_ops(int p, double rcond);
+// device_svd: the two pseudo-inverses on the GPU (pinv_truncated_device);
+// everything else on the host.
+HostOps* build_host_ops(int p, double rcond, bool device_svd = false);
+
+// Persistent operator cache: a binary file holding every table of a HostOps
+// with its key (p, rcond, the surface radii) and an FNV-1a checksum.
+// save throws Error(EINVAL) if the file cannot be written; load throws
+// Error(EINVAL) if it cannot be read, is not such a file, is damaged, or holds
+// operators of another key.
+void save_host_ops(const HostOps& ops, const char* path);
+HostOps* load_host_ops(const char* path, int p, double rcond);
 
 // M2L folded with the upward solve: m2l[o] * uc2e for every offset, FP64,
-// [316][n][n].  Maps a source box's scaled upward check potential straight
-// to the target's scaled downward check potential.
-std::vector<double> m2l_check_form(const HostOps& ops);
+// [316][n][n], on the current GPU (one batched FP64 GEMM).  Maps a source
+// box's scaled upward check potential straight to the target's scaled
+// downward check potential.
+std::vector<double> m2l_check_form_device(const HostOps& ops);
+
+// pinv_truncated on the GPU: rocSOLVER SVD, truncated product in one kernel.
+std::vector<double> pinv_truncated_device(const double* a, int n, double rcond, int* rank = nullptr);
+
 
 // One-sided Jacobi SVD of the square row-major matrix a [n][n]:
 // a = U diag(s) V^T; outputs U, V row-major [n][n], s descending.

@@ -44,7 +44,7 @@ _lib = None
 EXPORTED = [
     "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
-    "kifmm_precompute_operators",
+    "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_ops_save", "kifmm_ops_load",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
@@ -68,6 +68,9 @@ def lib():
     L.kifmm_tree_export_perm.argtypes = [P, P, P]
     L.kifmm_tree_update_points.argtypes = [P, P, P, P]
     L.kifmm_precompute_operators.argtypes = [I32, C.c_double, C.POINTER(P)]
+    L.kifmm_precompute_operators_ex.argtypes = [I32, C.c_double, I32, C.POINTER(P)]
+    L.kifmm_ops_save.argtypes = [P, C.c_char_p]
+    L.kifmm_ops_load.argtypes = [C.c_char_p, I32, C.c_double, C.POINTER(P)]
     L.kifmm_ops_export.argtypes = [P, I32, D, I64]
     L.kifmm_ops_n.argtypes = [P]
     L.kifmm_ops_n.restype = I32
@@ -186,13 +189,43 @@ class Tree:
 class Operators:
     """Operator tables of order p (host FP64; uploaded on first use)."""
 
-    def __init__(self, p: int, rcond: float = 1e-9):
+    def __init__(self, p: int, rcond: float = 1e-9, *, device_svd: bool = False, _handle=None):
         h = C.c_void_p()
-        _check(lib().kifmm_precompute_operators(p, rcond, C.byref(h)))
+        if _handle is not None:
+            h = _handle
+        elif device_svd:
+            _check(lib().kifmm_precompute_operators_ex(p, rcond, 1, C.byref(h)))
+        else:
+            _check(lib().kifmm_precompute_operators(p, rcond, C.byref(h)))
         self._h = h
         self.p = p
         self.rcond = rcond
         self.n = lib().kifmm_ops_n(h)
+
+    def save(self, path: str):
+        """Writes the operator cache file (kifmm_ops_save)."""
+        _check(lib().kifmm_ops_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str, p: int, rcond: float = 1e-9) -> "Operators":
+        """Reads an operator cache file of exactly (p, rcond) (kifmm_ops_load)."""
+        h = C.c_void_p()
+        _check(lib().kifmm_ops_load(os.fsencode(path), p, rcond, C.byref(h)))
+        return cls(p, rcond, _handle=h)
+
+    @classmethod
+    def cached(cls, p: int, rcond: float = 1e-9, cache_dir: str = ".", device_svd: bool = False) -> "Operators":
+        """Loads the operators of (p, rcond) from cache_dir, or computes and
+        saves them there."""
+        path = os.path.join(cache_dir, f"kifmm_ops_p{p}_rcond{rcond:.3e}.bin")
+        if os.path.exists(path):
+            try:
+                return cls.load(path, p, rcond)
+            except KifmmError:
+                pass  # damaged or foreign: computed again below
+        ops = cls(p, rcond, device_svd=device_svd)
+        ops.save(path)
+        return ops
 
     @property
     def handle(self):

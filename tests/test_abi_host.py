@@ -198,3 +198,40 @@ def test_tuning_keys_validated():
     finally:
         for k, v in defaults.items():
             K.set_tuning(k, v)
+
+
+def test_operator_cache_roundtrip_and_rejections(tmp_path):
+    """kifmm_ops_save / kifmm_ops_load (host only): a saved cache loads back
+    bitwise equal under its own key and is refused under another key, when
+    damaged, truncated, foreign or missing."""
+    ops = K.Operators(4)
+    path = str(tmp_path / "ops4.bin")
+    ops.save(path)
+    back = K.Operators.load(path, 4)
+    for which in range(7):
+        np.testing.assert_array_equal(back.export(which), ops.export(which))
+    with pytest.raises(K.KifmmError, match="another key"):
+        K.Operators.load(path, 5)
+    with pytest.raises(K.KifmmError, match="another key"):
+        K.Operators.load(path, 4, rcond=1e-8)
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0x40
+    bad = tmp_path / "damaged.bin"
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(K.KifmmError, match="checksum"):
+        K.Operators.load(str(bad), 4)
+    short = tmp_path / "short.bin"
+    short.write_bytes(open(path, "rb").read()[:1000])
+    with pytest.raises(K.KifmmError, match="truncated"):
+        K.Operators.load(str(short), 4)
+    foreign = tmp_path / "foreign.bin"
+    foreign.write_bytes(b"not an operator file at all")
+    with pytest.raises(K.KifmmError, match="not an operator cache"):
+        K.Operators.load(str(foreign), 4)
+    with pytest.raises(K.KifmmError, match="cannot read"):
+        K.Operators.load(str(tmp_path / "missing.bin"), 4)
+    # the cache helper computes once, then loads
+    a = K.Operators.cached(3, cache_dir=str(tmp_path))
+    b = K.Operators.cached(3, cache_dir=str(tmp_path))
+    np.testing.assert_array_equal(a.export(1), b.export(1))
+    assert K.lib().kifmm_precompute_operators_ex(4, 1e-9, 2, None) == 1  # EINVAL
