@@ -362,15 +362,21 @@ def main():
         result["gradient"] = {"ms_per_step": tg * 1e3, "Mpoints_per_s": n / tg / 1e6,
                               "rel_l2_vs_fp64_gpu": rel(g[1:], g64[1:])}
 
-    if not batch and prob.uniform_depth >= 0 and prob.halfwidth > 0:
+    if not batch:
         # the tree's points re-sorted on the device after each point moves to
         # a fresh position inside its leaf (kifmm_tree_update_points), against
         # the host build above; the original points are put back afterwards
-        cells = 2 ** prob.uniform_depth
-        lo = np.asarray(prob.center) - prob.halfwidth
-        t = (prob.points - lo) / (2 * prob.halfwidth)
-        c = np.clip(np.floor(t * cells), 0, cells - 1)
-        moved = lo + (c + np.random.default_rng(7).random(c.shape)) / cells * (2 * prob.halfwidth)
+        bx, inf = tree.boxes(), tree.info()
+        sperm, _ = tree.perm()
+        lo = np.asarray(inf.root_center) - inf.root_halfwidth
+        u = np.random.default_rng(7).random((inf.n_src, 3))
+        moved = np.empty((inf.n_src, 3))
+        for b in np.nonzero(bx["is_leaf"] == 1)[0]:
+            s0, s1 = bx["src_range"][b]
+            if s1 > s0:
+                idx = sperm[s0:s1]
+                w = 2 * inf.root_halfwidth / 2 ** int(bx["level"][b])
+                moved[idx] = lo + (bx["anchor"][b] + u[idx]) * w
         x_new = torch.as_tensor(moved, dtype=torch.float64, device=dev)
         x_old = torch.as_tensor(prob.points, dtype=torch.float64, device=dev)
         tree.update_points(x_new)

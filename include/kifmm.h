@@ -129,13 +129,16 @@ kifmm_status kifmm_tree_export_perm(const kifmm_tree* tree, int64_t* src_perm,
 /* Re-sort new positions of the tree's points on the GPU (the part of the
  * tree build that depends on the points: the linear octree of section
  * "Data-oriented design" keeps points sorted by the Morton key of their leaf,
- * boxes as ranges of that order).  For a uniform tree (uniform_depth 0..10)
- * whose points stay in the leaves they occupied, boxes, interaction lists and
- * evaluation plans are unchanged; the sorted order, the leaf-relative
- * coordinates and the box ranges are recomputed on the device with the host
- * build's rules (keys from the tree's root cube, clamped at its faces; a
- * stable sort, ties in caller order), so the tree equals kifmm_build_tree on
- * the new points with the same root, bit for bit.
+ * boxes as ranges of that order).  While every point stays in a leaf that
+ * held points of its kind (sources, targets) before and no such leaf
+ * empties, boxes, interaction lists and evaluation plans are unchanged; the
+ * sorted order, the leaf-relative coordinates and the box ranges are
+ * recomputed on the device with the host build's rules (keys at the tree's
+ * key level from its root cube, clamped at its faces; a stable sort, ties in
+ * caller order).  Uniform trees then equal kifmm_build_tree on the new
+ * points with the same root, bit for bit; so do adaptive trees whose fresh
+ * build would refine the same way (no leaf crossing n_crit), and otherwise
+ * they keep their boxes, which remains a valid FMM tree for the new points.
  * src_xyz: device FP64 [n_src][3], n_src as built.  tgt_xyz: device FP64
  * [n_tgt][3]; NULL if the tree was built with tgt_xyz == src_xyz (the targets
  * are the sources).  hip_stream: stream the work runs on (NULL: default); the
@@ -143,8 +146,8 @@ kifmm_status kifmm_tree_export_perm(const kifmm_tree* tree, int64_t* src_perm,
  * in place (its plans and a captured graph stay valid); the host copy
  * (exports, new plans) is refreshed on first use.
  * Errors: EINVAL (null tree, host pointers, missing targets, or a point in a
- * leaf cell that held no point of its kind before: the tree is unchanged;
- * build a new tree), EUNSUPPORTED (adaptive tree, depth > 10), EDEVICE. */
+ * leaf cell that held no point of its kind before, or an occupied leaf left
+ * empty: the tree is unchanged; build a new tree), EDEVICE. */
 kifmm_status kifmm_tree_update_points(kifmm_tree* tree, const double* src_xyz,
                                       const double* tgt_xyz, void* hip_stream);
 

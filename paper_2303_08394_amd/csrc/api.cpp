@@ -214,6 +214,7 @@ kifmm_status kifmm_tree_update_points(kifmm_tree* tree, const double* src_xyz, c
     EvalState* st = tree->state.get();
     PendingPoints* p = update_points_device(*tree->host, st, src_xyz, tgt_xyz, hip_stream);
     purge_batches(tree, nullptr);
+    if (tgt_xyz && tgt_xyz != src_xyz) tree->host->tgt_is_src = false;
     if (tree->pending) pending_free(tree->pending);
     tree->pending = p;
     // no forest on this device took the new order in place: refresh the

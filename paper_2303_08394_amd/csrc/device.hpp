@@ -70,14 +70,15 @@ struct DevPointView {
 };
 DevPointView dev_point_view(const EvalState& st);
 
-// New point positions of a uniform tree, sorted on the device (see
+// New point positions of a tree, sorted on the device (see
 // tree_update.hip) and held there until the host copy of the tree is
 // refreshed from them.
 struct PendingPoints;
 // Sorts src (and tgt; null: the sources) into T's leaves on the device and,
 // if st has a forest resident on the current device, rewrites it in place.
-// Throws Error: EINVAL if a point falls in another leaf set than T's (T and
-// st unchanged), EUNSUPPORTED for a non-uniform tree.  Synchronises stream.
+// Throws Error EINVAL if a point falls outside the leaves of its kind that
+// were occupied, or one of those empties (T and st unchanged).  Synchronises
+// the stream.
 PendingPoints* update_points_device(const HostTree& T, EvalState* st, const double* src, const double* tgt,
                                     void* stream);
 // Copies the sorted order, coordinates, keys and box ranges into T.

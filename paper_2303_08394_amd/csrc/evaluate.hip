@@ -701,11 +701,13 @@ struct P2PArgs {
   int grad;  // leaf kernel: also the gradient (pot holds [n_rhs][4][ntgt])
 };
 
-template <class T, int RC>
+template <class T, int RC, bool LO = false>
 struct P2PCfg {
   static constexpr int NT = 256;
-  // staged source: position (+ the charge in w when RC == 1), charges of RC > 1 columns
-  static constexpr int PB = int(sizeof(typename V4<T>::type)) + (RC > 1 ? RC * int(sizeof(T)) : 0);
+  // staged source: position (+ the charge in w when RC == 1), charges of RC > 1
+  // columns; with LO the FP32 rounding error of the position as well
+  static constexpr int PB = int(sizeof(typename V4<T>::type)) + (RC > 1 ? RC * int(sizeof(T)) : 0) +
+                            (LO ? int(sizeof(typename V4<T>::type)) : 0);
   // The batch size depends on T only, so every right-hand side sees the same
   // summation order whatever RC is (multi-RHS columns equal single runs bitwise).
   static constexpr int CAP = sizeof(T) == 4 ? 1024 : 512;
@@ -774,18 +776,26 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
                           const double (&ty)[kNch], const double (&tz)[kNch], int nchunks,
                           double (&acc)[kNch][RC], double (&gacc)[kNch][3]) {
   static_assert(!GRAD || RC == 1, "gradients are summed for one right-hand side per block");
-  using C = P2PCfg<U, RC>;
+  // Gradient terms cancel strongly between neighbours (points on a surface):
+  // in FP32 the differences x - y then take the positions as two-float sums
+  // (hi + lo), so that they are not limited by the rounding of coordinates.
+  constexpr bool LO = GRAD && sizeof(U) == 4;
+  using C = P2PCfg<U, RC, LO>;
   using V = typename V4<U>::type;
   constexpr int NT = 256, SL = NT / TCH, CAP = C::CAP;
   V* s_pos = reinterpret_cast<V*>(smem);
   U* s_q = reinterpret_cast<U*>(smem + CAP * sizeof(V));
+  V* s_lo = reinterpret_cast<V*>(smem + CAP * sizeof(V));  // (LO only, RC == 1)
   const int tid = threadIdx.x, sl = tid / TCH;
-  U ux[kNch], uy[kNch], uz[kNch];
+  U ux[kNch], uy[kNch], uz[kNch], lx[kNch], ly[kNch], lz[kNch];
 #pragma unroll
   for (int c = 0; c < kNch; ++c) {
     ux[c] = U(tx[c]);
     uy[c] = U(ty[c]);
     uz[c] = U(tz[c]);
+    lx[c] = U(tx[c] - double(ux[c]));
+    ly[c] = U(ty[c] - double(uy[c]));
+    lz[c] = U(tz[c] - double(uz[c]));
   }
   for (int sw = s0; sw < s1; sw += kMaxSeg) {
     const int nw = min(kMaxSeg, s1 - sw);
@@ -871,6 +881,14 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
         v.z = U(pz);
         v.w = q0;  // one right-hand side: the charge rides along with the position
         s_pos[j] = v;
+        if constexpr (LO) {
+          V l;
+          l.x = U(px - double(v.x));
+          l.y = U(py - double(v.y));
+          l.z = U(pz - double(v.z));
+          l.w = U(0);
+          s_lo[j] = l;
+        }
       }
       __syncthreads();
 #pragma unroll
@@ -879,11 +897,17 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
           U part[RC], gpart[3] = {U(0), U(0), U(0)};
 #pragma unroll
           for (int r = 0; r < RC; ++r) part[r] = U(0);
-          const U x = ux[c], y = uy[c], z = uz[c];
+          const U x = ux[c], y = uy[c], z = uz[c], xl = lx[c], yl = ly[c], zl = lz[c];
           // sources j = sl, sl + SL, ... in order; four per trip so that their
           // LDS reads are in flight together (same summation order)
           auto pair = [&](const V& s, int j, auto checked) __attribute__((always_inline)) {
-            const U dx = x - s.x, dy = y - s.y, dz = z - s.z;
+            U dx = x - s.x, dy = y - s.y, dz = z - s.z;
+            if constexpr (LO) {
+              const V l = s_lo[j];
+              dx += xl - l.x;
+              dy += yl - l.y;
+              dz += zl - l.z;
+            }
             const U r2 = dx * dx + dy * dy + dz * dz;
             U ri;
             if constexpr (decltype(checked)::value) ri = rinv(r2);   // coincident pair -> 0
@@ -963,8 +987,8 @@ template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
   constexpr int NT = 256, SL = NT / TCH;
   static_assert(!GRAD || (MODE == MODE_LEAF && RC == 1), "gradients: leaf kernel, one right-hand side");
-  constexpr int SMEM0 = P2PCfg<T, RC>::BYTES > P2PCfg<TF, RC>::BYTES ? P2PCfg<T, RC>::BYTES
-                                                                     : P2PCfg<TF, RC>::BYTES;
+  constexpr int SMEM0 = P2PCfg<T, RC, GRAD>::BYTES > P2PCfg<TF, RC, GRAD>::BYTES ? P2PCfg<T, RC, GRAD>::BYTES
+                                                                                 : P2PCfg<TF, RC, GRAD>::BYTES;
   constexpr int NV = RC + (GRAD ? 3 : 0);  // reduced values per target
   constexpr int RED = NT * NV * 8;
   __shared__ __align__(16) unsigned char smem[SMEM0 > RED ? SMEM0 : RED];

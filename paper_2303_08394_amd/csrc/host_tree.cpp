@@ -370,7 +370,6 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
     }
     for (int d = 0; d < 3; ++d) T.lo[d] = T.c0[d] - T.r0;
     T.key_level = prm.uniform_depth >= 0 ? prm.uniform_depth : prm.max_depth;
-    T.uniform = prm.uniform_depth >= 0;
     T.tgt_is_src = tgt == src && ntgt == nsrc;
 
     sort_points(src, nsrc, T.lo, T.r0, T.key_level, T.sperm, T.sxyz, T.skey);

@@ -23,7 +23,6 @@ struct HostTree {
 
   double c0[3] = {0, 0, 0}, r0 = 0, lo[3] = {0, 0, 0};
   int key_level = 0;  // level of the point keys (uniform depth or max depth)
-  bool uniform = false;     // built with a uniform depth (every leaf at key_level)
   bool tgt_is_src = false;  // the targets were given as the source array
   int depth = 0;      // deepest level holding a box
 

@@ -1,14 +1,15 @@
-// New point positions sorted into an existing uniform tree on the GPU: the
-// part of the tree build that depends on the points (section "Data-oriented
-// design": the linear octree keeps its points sorted by the Morton key of
-// their leaf, and boxes as ranges of that order).  For a uniform tree whose
-// occupied leaves stay the same, the boxes, interaction lists and tile plans
-// do not change; only the point order, the leaf-relative coordinates and the
-// box ranges do.  Every rule follows the host build exactly (FP64, no
-// contraction), so the result equals building the tree again on the host.
+// New point positions sorted into an existing tree on the GPU: the part of
+// the tree build that depends on the points (section "Data-oriented design":
+// the linear octree keeps its points sorted by the Morton key of their leaf,
+// and boxes as ranges of that order).  While every point stays in a leaf of
+// its kind (sources, targets) that was occupied before, and no occupied leaf
+// empties, the boxes, interaction lists and tile plans do not change; only
+// the point order, the leaf-relative coordinates and the box ranges do.
+// Every rule follows the host build exactly (FP64, no contraction).
 //
 //   key      clamp(floor(t * 2^L), 0, 2^L - 1) per axis, t = (x - lo) / (2 r0),
-//            interleaved x-major (30 bits: L <= 10);
+//            interleaved x-major at the key level L (the uniform depth, or the
+//            maximum depth of an adaptive tree: up to 60 bits);
 //   order    stable LSD radix sort of the keys, 8 bits per pass, ties in the
 //            caller's order;
 //   ranges   box b at level l holds the keys [m << 3(L-l), (m+1) << 3(L-l))
@@ -31,55 +32,46 @@ namespace {
 constexpr int kThreads = 256;   // = the 256 digits of a pass
 constexpr int kItems = 16;      // keys per thread and block tile
 constexpr int kTile = kThreads * kItems;
-constexpr int kMaxUpdateLevel = 10;
+typedef unsigned long long u64;
 
-__device__ inline uint32_t spread3(uint32_t v) {  // bit k of v -> bit 3k (k < 10)
-  v &= 0x3ffu;
-  v = (v | (v << 16)) & 0xff0000ffu;
-  v = (v | (v << 8)) & 0x0300f00fu;
-  v = (v | (v << 4)) & 0x030c30c3u;
-  v = (v | (v << 2)) & 0x09249249u;
+__device__ inline u64 spread3(u64 v) {  // bit k of v -> bit 3k (k < 21)
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
   return v;
 }
-__device__ inline uint32_t compact3(uint32_t v) {  // inverse of spread3
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030c30c3u;
-  v = (v | (v >> 4)) & 0x0300f00fu;
-  v = (v | (v >> 8)) & 0xff0000ffu;
-  v = (v | (v >> 16)) & 0x000003ffu;
-  return v;
-}
-__device__ inline uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-  return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
-}
+__device__ inline u64 morton3(u64 x, u64 y, u64 z) { return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z); }
 
 struct Frame {
   double lo[3];
-  double r0, rL;  // root half-width, leaf half-width r0 / 2^L
-  int L;
+  double r0;  // root half-width
+  int L;      // key level
 };
 
-__global__ void key_kernel(const double* __restrict__ xyz, int64_t n, Frame f, uint32_t* __restrict__ keys,
+__global__ void key_kernel(const double* __restrict__ xyz, int64_t n, Frame f, u64* __restrict__ keys,
                            int32_t* __restrict__ idx) {
 #pragma clang fp contract(off)
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double cells = double(1 << f.L), maxi = cells - 1.0;
-  uint32_t ix[3];
+  const double cells = double(int64_t(1) << f.L), maxi = cells - 1.0;
+  u64 ix[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double t = (xyz[3 * i + d] - f.lo[d]) / (2.0 * f.r0);
     double c = floor(t * cells);
     if (!(c >= 0.0)) c = 0.0;
     if (c > maxi) c = maxi;
-    ix[d] = uint32_t(c);
+    ix[d] = u64(c);
   }
   keys[i] = morton3(ix[0], ix[1], ix[2]);
   idx[i] = int32_t(i);
 }
 
 // Digit counts of each block's tile, stored digit-major: hist[digit][block].
-__global__ void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, int shift,
+__global__ void radix_hist_kernel(const u64* __restrict__ keys, int64_t n, int shift,
                                   uint32_t* __restrict__ hist, int nblk) {
   __shared__ uint32_t h[kThreads];
   const int tid = threadIdx.x;
@@ -88,7 +80,7 @@ __global__ void radix_hist_kernel(const uint32_t* __restrict__ keys, int64_t n, 
   const int64_t base = int64_t(blockIdx.x) * kTile;
   for (int k = 0; k < kItems; ++k) {
     const int64_t i = base + k * kThreads + tid;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    if (i < n) atomicAdd(&h[unsigned(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
   hist[int64_t(tid) * nblk + blockIdx.x] = h[tid];
@@ -127,8 +119,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(uint32_t* a, int64_t m) {
 // for the block + the counts of its digit in lower waves of the chunk + its
 // rank among the lanes of its wave with the same digit (found with ballots).
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
-    const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
-    const uint32_t* __restrict__ hist, int nblk, uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+    const u64* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
+    const uint32_t* __restrict__ hist, int nblk, u64* __restrict__ kout, int32_t* __restrict__ vout) {
   constexpr int NW = kThreads / 64;
   __shared__ uint32_t base[kThreads];
   __shared__ uint32_t wcnt[NW][kThreads];
@@ -141,9 +133,9 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     __syncthreads();
     const int64_t i = t0 + k * kThreads + tid;
     const bool valid = i < n;  // invalid lanes only follow valid ones
-    const uint32_t key = valid ? kin[i] : 0xffffffffu;
+    const u64 key = valid ? kin[i] : ~0ull;
     const int32_t val = valid ? vin[i] : 0;
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t d = unsigned(key >> shift) & 255u;
     unsigned long long peers = ~0ull;
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -169,32 +161,38 @@ __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
   }
 }
 
-// Sorted raw coordinates and leaf-frame coordinates of every sorted point.
-__global__ void place_kernel(const double* __restrict__ xyz, const uint32_t* __restrict__ skeys,
-                             const int32_t* __restrict__ perm, int64_t n, Frame f,
-                             double* __restrict__ sorted_xyz, double4* __restrict__ rel) {
-#pragma clang fp contract(off)
+// Sorted raw coordinates of every sorted point.
+__global__ void gather_sorted_kernel(const double* __restrict__ xyz, const int32_t* __restrict__ perm, int64_t n,
+                                     double* __restrict__ sorted_xyz) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t j = perm[i];
-  const uint32_t key = skeys[i];
-  const uint32_t a[3] = {compact3(key >> 2), compact3(key >> 1), compact3(key)};
-  double r[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double x = xyz[3 * j + d];
-    const double c = f.lo[d] + (2.0 * double(a[d]) + 1.0) * f.rL;
-    r[d] = (x - c) / f.rL;
-    sorted_xyz[3 * i + d] = x;
-  }
-  rel[i] = make_double4(r[0], r[1], r[2], 0.0);
+  for (int d = 0; d < 3; ++d) sorted_xyz[3 * i + d] = xyz[3 * j + d];
 }
 
-__device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t n, uint64_t v) {
+// Leaf-frame coordinates (x - c) / r of the points of each leaf (one block
+// per leaf box; c and r from its anchor and level, as the host computes them).
+__global__ void leaf_frame_kernel(const int32_t* __restrict__ leaves, const int32_t* __restrict__ anchor,
+                                  const int32_t* __restrict__ level, const int2* __restrict__ ranges, Frame f,
+                                  const double* __restrict__ sorted_xyz, double4* __restrict__ rel) {
+#pragma clang fp contract(off)
+  const int g = leaves[blockIdx.x];
+  const int2 rg = ranges[g];
+  const double r = f.r0 / double(int64_t(1) << level[g]);
+  double c[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) c[d] = f.lo[d] + (2.0 * double(anchor[3 * g + d]) + 1.0) * r;
+  for (int i = rg.x + threadIdx.x; i < rg.y; i += blockDim.x)
+    rel[i] = make_double4((sorted_xyz[3 * i] - c[0]) / r, (sorted_xyz[3 * i + 1] - c[1]) / r,
+                          (sorted_xyz[3 * i + 2] - c[2]) / r, 0.0);
+}
+
+__device__ inline int64_t lower_bound_u64(const u64* a, int64_t n, u64 v) {
   int64_t lo = 0, hi = n;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if (uint64_t(a[mid]) < v) lo = mid + 1;
+    if (a[mid] < v) lo = mid + 1;
     else hi = mid;
   }
   return lo;
@@ -204,16 +202,16 @@ __device__ inline int64_t lower_bound_u32(const uint32_t* a, int64_t n, uint64_t
 // counts the points that fall in leaves.
 __global__ void ranges_kernel(const int32_t* __restrict__ anchor, const int32_t* __restrict__ level,
                               const int32_t* __restrict__ is_leaf, const int64_t* __restrict__ old_rng,
-                              int32_t nbox, int L, const uint32_t* __restrict__ skeys, int64_t n,
+                              int32_t nbox, int L, const u64* __restrict__ skeys, int64_t n,
                               int2* __restrict__ out, unsigned* __restrict__ flag,
                               unsigned long long* __restrict__ in_leaves) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= nbox) return;
   const int l = level[g];
-  const uint64_t m = morton3(uint32_t(anchor[3 * g]), uint32_t(anchor[3 * g + 1]), uint32_t(anchor[3 * g + 2]));
+  const u64 m = morton3(u64(anchor[3 * g]), u64(anchor[3 * g + 1]), u64(anchor[3 * g + 2]));
   const int sh = 3 * (L - l);
-  const int64_t b = lower_bound_u32(skeys, n, m << sh);
-  const int64_t e = lower_bound_u32(skeys, n, (m + 1) << sh);
+  const int64_t b = lower_bound_u64(skeys, n, m << sh);
+  const int64_t e = lower_bound_u64(skeys, n, (m + 1) << sh);
   out[g] = make_int2(int(b), int(e));
   if (is_leaf[g]) {
     const bool was = old_rng[2 * g + 1] > old_rng[2 * g];
@@ -235,7 +233,7 @@ T* dalloc(std::vector<void*>& owned, size_t count) {
 // One sorted point set, resident on the device until copied to the host.
 struct SortedSet {
   int64_t n = 0;
-  uint32_t* keys = nullptr;    // [n] sorted leaf keys
+  u64* keys = nullptr;         // [n] sorted leaf keys
   int32_t* perm = nullptr;     // [n] sorted position -> caller index
   double* xyz = nullptr;       // [n][3] sorted coordinates
   double4* rel = nullptr;      // [n] leaf-frame coordinates
@@ -254,27 +252,34 @@ struct PendingPoints {
   }
 };
 
+struct FreeAll {
+  std::vector<void*> v;
+  ~FreeAll() {
+    for (void* p : v) (void)hipFree(p);
+  }
+};
+
 static void sort_set(const HostTree& T, const double* xyz, int64_t n, const std::vector<int64_t>& old_rng,
-                     const int32_t* d_anchor, const int32_t* d_level, const int32_t* d_leaf, hipStream_t s,
-                     SortedSet& S, unsigned* d_flag, unsigned long long* d_count) {
+                     const int32_t* d_anchor, const int32_t* d_level, const int32_t* d_leaf,
+                     const int32_t* d_leaves, int nleaves, hipStream_t s, SortedSet& S, unsigned* d_flag,
+                     unsigned long long* d_count) {
   Frame f;
   for (int d = 0; d < 3; ++d) f.lo[d] = T.lo[d];
   f.r0 = T.r0;
   f.L = T.key_level;
-  f.rL = T.halfwidth(T.key_level);
   S.n = n;
-  std::vector<void*> tmp;
-  uint32_t* k0 = dalloc<uint32_t>(tmp, n);
-  int32_t* v0 = dalloc<int32_t>(tmp, n);
-  uint32_t* k1 = dalloc<uint32_t>(S.owned, n);
+  FreeAll tmp;
+  u64* k0 = dalloc<u64>(tmp.v, n);
+  int32_t* v0 = dalloc<int32_t>(tmp.v, n);
+  u64* k1 = dalloc<u64>(S.owned, n);
   int32_t* v1 = dalloc<int32_t>(S.owned, n);
   const unsigned grid = unsigned((n + 255) / 256);
   hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, k0, v0);
   LAUNCHCHECK("key_kernel");
   const int nblk = int((n + kTile - 1) / kTile);
-  uint32_t* hist = dalloc<uint32_t>(tmp, size_t(kThreads) * nblk);
+  uint32_t* hist = dalloc<uint32_t>(tmp.v, size_t(kThreads) * nblk);
   const int passes = (3 * T.key_level + 7) / 8;
-  uint32_t *kin = k0, *kout = k1;
+  u64 *kin = k0, *kout = k1;
   int32_t *vin = v0, *vout = v1;
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, n, 8 * p, hist, nblk);
@@ -289,31 +294,32 @@ static void sort_set(const HostTree& T, const double* xyz, int64_t n, const std:
   }
   // the sorted keys and order are in (kin, vin): keep those buffers
   if (kin == k0) {
-    HIPCHECK(hipMemcpyAsync(k1, k0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(k1, k0, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemcpyAsync(v1, v0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   }
   S.keys = k1;
   S.perm = v1;
   S.xyz = dalloc<double>(S.owned, size_t(n) * 3);
   S.rel = dalloc<double4>(S.owned, n);
-  hipLaunchKernelGGL(place_kernel, dim3(grid), dim3(256), 0, s, xyz, S.keys, S.perm, n, f, S.xyz, S.rel);
-  LAUNCHCHECK("place_kernel");
-  int64_t* d_old = dalloc<int64_t>(tmp, old_rng.size());
+  hipLaunchKernelGGL(gather_sorted_kernel, dim3(grid), dim3(256), 0, s, xyz, S.perm, n, S.xyz);
+  LAUNCHCHECK("gather_sorted_kernel");
+  int64_t* d_old = dalloc<int64_t>(tmp.v, old_rng.size());
   HIPCHECK(hipMemcpyAsync(d_old, old_rng.data(), old_rng.size() * 8, hipMemcpyHostToDevice, s));
   S.ranges = dalloc<int2>(S.owned, T.nbox);
   hipLaunchKernelGGL(ranges_kernel, dim3(unsigned((T.nbox + 255) / 256)), dim3(256), 0, s, d_anchor, d_level,
                      d_leaf, d_old, T.nbox, T.key_level, S.keys, n, S.ranges, d_flag, d_count);
   LAUNCHCHECK("ranges_kernel");
-  // the host copy of old_rng must outlive the copy above
+  if (nleaves > 0) {
+    hipLaunchKernelGGL(leaf_frame_kernel, dim3(unsigned(nleaves)), dim3(64), 0, s, d_leaves, d_anchor, d_level,
+                       S.ranges, f, S.xyz, S.rel);
+    LAUNCHCHECK("leaf_frame_kernel");
+  }
+  // the host copy of old_rng and the scratch must outlive the work above
   HIPCHECK(hipStreamSynchronize(s));
-  for (void* p : tmp) (void)hipFree(p);
 }
 
 PendingPoints* update_points_device(const HostTree& T, EvalState* st, const double* src, const double* tgt,
                                     void* stream) {
-  if (!T.uniform) raise(KIFMM_EUNSUPPORTED, "update_points: the tree is not uniform");
-  if (T.key_level > kMaxUpdateLevel)
-    raise(KIFMM_EUNSUPPORTED, "update_points: uniform depth above 10");
   if (!src) raise(KIFMM_EINVAL, "update_points: null source coordinates");
   if (!tgt && !T.tgt_is_src)
     raise(KIFMM_EINVAL, "update_points: the tree has separate targets; pass their coordinates");
@@ -330,21 +336,21 @@ PendingPoints* update_points_device(const HostTree& T, EvalState* st, const doub
   P->device = current_device();
   P->nbox = T.nbox;
   P->tgt_is_src = tgt == nullptr;
-  std::vector<void*> tmp;
-  struct Guard {
-    std::vector<void*>& v;
-    ~Guard() {
-      for (void* p : v) (void)hipFree(p);
-    }
-  } guard{tmp};
+  FreeAll tmp;
   std::vector<int32_t> isleaf(T.leaf.begin(), T.leaf.end());
-  int32_t* d_anchor = dalloc<int32_t>(tmp, T.anchor.size());
-  int32_t* d_level = dalloc<int32_t>(tmp, T.level.size());
-  int32_t* d_leaf = dalloc<int32_t>(tmp, isleaf.size());
-  unsigned long long* d_stat = dalloc<unsigned long long>(tmp, 4);  // flag (as unsigned), count per set
+  std::vector<int32_t> leaves;
+  for (int32_t g = 0; g < T.nbox; ++g)
+    if (T.leaf[g]) leaves.push_back(g);
+  int32_t* d_anchor = dalloc<int32_t>(tmp.v, T.anchor.size());
+  int32_t* d_level = dalloc<int32_t>(tmp.v, T.level.size());
+  int32_t* d_leaf = dalloc<int32_t>(tmp.v, isleaf.size());
+  int32_t* d_leaves = dalloc<int32_t>(tmp.v, leaves.size());
+  unsigned long long* d_stat = dalloc<unsigned long long>(tmp.v, 4);  // flag (as unsigned), count per set
   HIPCHECK(hipMemcpyAsync(d_anchor, T.anchor.data(), T.anchor.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(d_level, T.level.data(), T.level.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(d_leaf, isleaf.data(), isleaf.size() * 4, hipMemcpyHostToDevice, s));
+  if (!leaves.empty())
+    HIPCHECK(hipMemcpyAsync(d_leaves, leaves.data(), leaves.size() * 4, hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemsetAsync(d_stat, 0, 4 * sizeof(unsigned long long), s));
   unsigned* d_flag = reinterpret_cast<unsigned*>(d_stat);
   std::vector<int64_t> old(2 * size_t(T.nbox));
@@ -352,13 +358,15 @@ PendingPoints* update_points_device(const HostTree& T, EvalState* st, const doub
     old[2 * g] = T.sbeg[g];
     old[2 * g + 1] = T.send[g];
   }
-  sort_set(T, src, T.nsrc, old, d_anchor, d_level, d_leaf, s, P->src, d_flag, d_stat + 1);
+  sort_set(T, src, T.nsrc, old, d_anchor, d_level, d_leaf, d_leaves, int(leaves.size()), s, P->src, d_flag,
+           d_stat + 1);
   if (tgt) {
     for (int32_t g = 0; g < T.nbox; ++g) {
       old[2 * g] = T.tbeg[g];
       old[2 * g + 1] = T.tend[g];
     }
-    sort_set(T, tgt, T.ntgt, old, d_anchor, d_level, d_leaf, s, P->tgt, d_flag, d_stat + 2);
+    sort_set(T, tgt, T.ntgt, old, d_anchor, d_level, d_leaf, d_leaves, int(leaves.size()), s, P->tgt, d_flag,
+             d_stat + 2);
   }
   unsigned long long stat[4];
   HIPCHECK(hipMemcpyAsync(stat, d_stat, sizeof(stat), hipMemcpyDeviceToHost, s));
@@ -383,11 +391,11 @@ PendingPoints* update_points_device(const HostTree& T, EvalState* st, const doub
 
 static void set_to_host(const SortedSet& S, int32_t nbox, std::vector<int64_t>& perm, std::vector<double>& xyz,
                         std::vector<uint64_t>& keys, std::vector<int64_t>& beg, std::vector<int64_t>& end) {
-  std::vector<uint32_t> k(S.n);
+  std::vector<u64> k(S.n);
   std::vector<int32_t> p(S.n);
   std::vector<int2> r(nbox);
   xyz.resize(3 * size_t(S.n));
-  HIPCHECK(hipMemcpy(k.data(), S.keys, size_t(S.n) * 4, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(k.data(), S.keys, size_t(S.n) * 8, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(p.data(), S.perm, size_t(S.n) * 4, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(xyz.data(), S.xyz, size_t(S.n) * 24, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(r.data(), S.ranges, size_t(nbox) * 8, hipMemcpyDeviceToHost));

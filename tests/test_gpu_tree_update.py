@@ -1,13 +1,14 @@
-"""Device re-sort of a uniform tree's points (kifmm_tree_update_points)
-against the host build on the same points and the FP64 oracle.
+"""Device re-sort of a tree's points (kifmm_tree_update_points) against the
+host build on the same points and the FP64 oracle.
 
 Bit-exact where the work is integer or follows the host's FP64 rules: the
 sorted order, every box's point ranges, and the evaluation (equal inputs in
 equal order give equal potentials, bitwise).  The potentials of the updated
-tree also meet the oracle at the mixed-precision tolerance.  Cases cover one,
-two and three radix passes (depths 3, 5 and 6), a resident forest updated in
-place (also under graph replay) and one refreshed through the host copy,
-separate targets, and the rejected cases.
+tree also meet the oracle at the mixed-precision tolerance.  Cases cover two
+to eight radix passes (uniform depths 3, 5, 6; adaptive trees keyed at
+levels 10, 16 and 20), a resident forest updated in place (also under graph
+replay) and one refreshed through the host copy, separate targets, and the
+rejected cases.
 """
 import numpy as np
 import pytest
@@ -134,9 +135,6 @@ def test_update_rejects_other_leaves_and_keeps_tree():
     with pytest.raises(K.KifmmError, match="device memory"):  # host memory is refused
         K._check(L.kifmm_tree_update_points(tree.handle, K._dptr(x0), None, None))
     np.testing.assert_array_equal(evaluate(tree, q, p), before)
-    adaptive = K.Tree(x0, ncrit=64, max_depth=8)
-    with pytest.raises(K.KifmmError, match="uniform"):
-        adaptive.update_points(dev(x0))
 
 
 def test_update_fullsize_1m():
@@ -148,3 +146,38 @@ def test_update_fullsize_1m():
     tree.update_points(dev(x1))
     fresh = K.Tree(x1, uniform_depth=prob.uniform_depth, center=prob.center, halfwidth=prob.halfwidth)
     assert_same_tree(tree, fresh)
+
+
+def inside_own_leaves(tree, seed):
+    """New caller-order points, each drawn inside the leaf cube that holds the
+    old one: every leaf keeps its points (and its count)."""
+    bx, inf = tree.boxes(), tree.info()
+    sperm, _ = tree.perm()
+    lo = np.asarray(inf.root_center) - inf.root_halfwidth
+    n = inf.n_src
+    new = np.empty((n, 3))
+    u = np.random.default_rng(seed).random((n, 3))
+    for b in np.nonzero(bx["is_leaf"] == 1)[0]:
+        s0, s1 = bx["src_range"][b]
+        if s1 <= s0:
+            continue
+        w = 2 * inf.root_halfwidth / 2 ** int(bx["level"][b])
+        idx = sperm[s0:s1]
+        new[idx] = lo + (bx["anchor"][b] + u[idx]) * w
+    return new
+
+
+@pytest.mark.parametrize("max_depth,ncrit", [(10, 32), (16, 24), (20, 24)])
+def test_update_adaptive_equals_host_build(max_depth, ncrit):
+    x0, q = I.sphere_surface(20000, seed=100 + max_depth, jitter=0.0)
+    p = 4
+    tree = K.Tree(x0, ncrit=ncrit, max_depth=max_depth)
+    inf = tree.info()
+    evaluate(tree, q, p)
+    x1 = inside_own_leaves(tree, seed=7)
+    tree.update_points(dev(x1))
+    fresh = K.Tree(x1, ncrit=ncrit, max_depth=max_depth, center=tuple(inf.root_center),
+                   halfwidth=inf.root_halfwidth)
+    assert fresh.info().n_boxes == inf.n_boxes
+    assert_same_tree(tree, fresh)
+    np.testing.assert_array_equal(evaluate(tree, q, p), evaluate(fresh, q, p))
