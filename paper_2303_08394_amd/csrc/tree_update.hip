@@ -86,32 +86,58 @@ __global__ void radix_hist_kernel(const u64* __restrict__ keys, int64_t n, int s
   hist[int64_t(tid) * nblk + blockIdx.x] = h[tid];
 }
 
-// Exclusive prefix sum of a[0..m) in place, one block of 1024 threads
-// walking the array in chunks with a running carry.
-__global__ __launch_bounds__(1024) void scan_kernel(uint32_t* a, int64_t m) {
+// Exclusive prefix sum of a[0..m) in place, in three launches: each block
+// of 1024 threads scans its chunk (wave shuffles, then the waves' totals) and
+// records the chunk's total; one block scans those totals; every element
+// then adds its chunk's offset.
+__global__ __launch_bounds__(1024) void scan_chunks_kernel(uint32_t* a, int64_t m, uint32_t* totals) {
   __shared__ uint32_t wsum[16];
-  __shared__ uint32_t carry;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int64_t c0 = 0; c0 < m; c0 += 1024) {
-    const int64_t i = c0 + tid;
-    const uint32_t v = i < m ? a[i] : 0u;
-    uint32_t s = v;  // inclusive scan within the wave
+  const int64_t i = int64_t(blockIdx.x) * 1024 + tid;
+  const uint32_t v = i < m ? a[i] : 0u;
+  uint32_t s = v;  // inclusive scan within the wave
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const uint32_t t = __shfl_up(s, off, 64);
-      if (lane >= off) s += t;
-    }
-    if (lane == 63) wsum[w] = s;
-    __syncthreads();
-    uint32_t before = carry;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (i < m) a[i] = before + s - v;
-    __syncthreads();
-    if (tid == 1023) carry = before + s;
-    __syncthreads();
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(s, off, 64);
+    if (lane >= off) s += t;
   }
+  if (lane == 63) wsum[w] = s;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  if (i < m) a[i] = before + s - v;
+  if (tid == 1023) totals[blockIdx.x] = before + s;
+}
+
+__global__ __launch_bounds__(1024) void scan_totals_kernel(uint32_t* totals, int n) {
+  // n <= 1024 * 64: each thread scans a run of consecutive totals
+  __shared__ uint32_t part[1024];
+  const int tid = threadIdx.x, per = (n + 1023) / 1024;
+  const int b = tid * per, e = min(n, b + per);
+  uint32_t sum = 0;
+  for (int k = b; k < e; ++k) sum += totals[k];
+  part[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < 1024; ++k) {
+      const uint32_t x = part[k];
+      part[k] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  uint32_t run = part[tid];
+  for (int k = b; k < e; ++k) {
+    const uint32_t x = totals[k];
+    totals[k] = run;
+    run += x;
+  }
+}
+
+__global__ void scan_add_kernel(uint32_t* a, int64_t m, const uint32_t* totals) {
+  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
+  if (i < m) a[i] += totals[blockIdx.x];
 }
 
 // Stable scatter of one pass.  Each block walks its tile in chunks of 256
@@ -278,14 +304,22 @@ static void sort_set(const HostTree& T, const double* xyz, int64_t n, const std:
   LAUNCHCHECK("key_kernel");
   const int nblk = int((n + kTile - 1) / kTile);
   uint32_t* hist = dalloc<uint32_t>(tmp.v, size_t(kThreads) * nblk);
+  const int64_t m = int64_t(kThreads) * nblk;  // scanned entries
+  const int nchunk = int((m + 1023) / 1024);
+  if (nchunk > 1024 * 64) raise(KIFMM_EUNSUPPORTED, "update_points: too many points for one sort");
+  uint32_t* totals = dalloc<uint32_t>(tmp.v, nchunk);
   const int passes = (3 * T.key_level + 7) / 8;
   u64 *kin = k0, *kout = k1;
   int32_t *vin = v0, *vout = v1;
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, n, 8 * p, hist, nblk);
     LAUNCHCHECK("radix_hist_kernel");
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, hist, int64_t(kThreads) * nblk);
-    LAUNCHCHECK("scan_kernel");
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, hist, m, totals);
+    LAUNCHCHECK("scan_chunks_kernel");
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(1024), 0, s, totals, nchunk);
+    LAUNCHCHECK("scan_totals_kernel");
+    hipLaunchKernelGGL(scan_add_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, hist, m, totals);
+    LAUNCHCHECK("scan_add_kernel");
     hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, vin, n, 8 * p, hist, nblk,
                        kout, vout);
     LAUNCHCHECK("radix_scatter_kernel");
