@@ -15,7 +15,8 @@ octree   the octree (uniform, adaptive, 2:1 balanced) and the U, V, W, X
          interaction lists (same section), written from their definitions.
 kifmm    O2: the KIFMM evaluation in FP64, step by step: P2M, M2M, M2L, P2L,
          L2L, L2P, M2P and the near field (section "The Fast Multipole Method");
-         optionally the gradient, from the kernel's derivative in the leaf stage.
+         optionally the gradient, from the kernel's derivative in the leaf stage;
+         optionally the screened (Yukawa) kernel exp(-kappa r) / (4 pi r).
 
 Parity status: every function is pinned by the CPU tests in
 ``tests/test_oracle_*.py`` (closed forms, brute force, invariants, exact

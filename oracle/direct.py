@@ -20,9 +20,12 @@ import numpy as np
 INV_4PI = 1.0 / (4.0 * np.pi)
 
 
-def kernel_matrix(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+def kernel_matrix(x: np.ndarray, y: np.ndarray, kappa: float = 0.0) -> np.ndarray:
     """K[i, j] = 1 / (4 pi |x_i - y_j|), and 0 where x_i == y_j (Eq. 1).
 
+    With kappa > 0 the screened (Yukawa) kernel exp(-kappa r) / (4 pi r): a
+    second kernel for the kernel-independent method (the paper's experiments
+    use the Laplace kernel only).
     x: (m, 3) evaluation points, y: (n, 3) source points, both float64.
     """
     x = np.asarray(x, dtype=np.float64)
@@ -32,13 +35,16 @@ def kernel_matrix(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     dz = x[:, None, 2] - y[None, :, 2]
     r2 = dx * dx + dy * dy + dz * dz
     with np.errstate(divide="ignore"):
-        k = INV_4PI / np.sqrt(r2)
+        r = np.sqrt(r2)
+        k = INV_4PI / r
+        if kappa != 0.0:
+            k = k * np.exp(-kappa * r)
     k[r2 == 0.0] = 0.0
     return k
 
 
 def direct(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
-           chunk: int = 2048) -> np.ndarray:
+           chunk: int = 2048, kappa: float = 0.0) -> np.ndarray:
     """Potentials at tgt due to charges at src, by the O(N^2) sum of Eq. (1).
 
     src (n_src, 3), tgt (n_tgt, 3) float64; charges (n_src,) or (n_rhs, n_src).
@@ -49,7 +55,7 @@ def direct(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
     q2 = q[None, :] if one else q
     out = np.zeros((q2.shape[0], len(tgt)))
     for s in range(0, len(tgt), chunk):
-        k = kernel_matrix(tgt[s:s + chunk], src)
+        k = kernel_matrix(tgt[s:s + chunk], src, kappa)
         out[:, s:s + chunk] = (k @ q2.T).T
     return out[0] if one else out
 

@@ -43,15 +43,23 @@ def pinv_truncated(a: np.ndarray, rcond: float) -> np.ndarray:
 class KIFMM:
     """FP64 KIFMM on an oracle Octree at expansion order p."""
 
-    def __init__(self, tree: Octree, p: int, rcond: float = 1e-9):
+    def __init__(self, tree: Octree, p: int, rcond: float = 1e-9, kappa: float = 0.0):
+        """kappa > 0: the screened (Yukawa) kernel exp(-kappa r) / (4 pi r)
+        in every operator (the method is kernel independent; its operators
+        are formed per level from the actual box sizes, which the screened
+        kernel needs: it is not homogeneous)."""
         if p < 2:
             raise ValueError("p must be >= 2")
         self.tree = tree
         self.p = p
         self.rcond = rcond
+        self.kappa = float(kappa)
         self.s = surface_grid(p)
         self.n = len(self.s)
         self._ops: dict = {}
+
+    def _k(self, x, y):
+        return kernel_matrix(x, y, self.kappa)
 
     # -- operators (one per level; translation-invariant ones keyed by offset)
     def _r(self, level):
@@ -62,7 +70,7 @@ class KIFMM:
         key = ("uc2e", level)
         if key not in self._ops:
             r = self._r(level)
-            k = kernel_matrix(RADIUS_OUTER * r * self.s, RADIUS_INNER * r * self.s)
+            k = self._k(RADIUS_OUTER * r * self.s, RADIUS_INNER * r * self.s)
             self._ops[key] = pinv_truncated(k, self.rcond)
         return self._ops[key]
 
@@ -71,7 +79,7 @@ class KIFMM:
         key = ("dc2e", level)
         if key not in self._ops:
             r = self._r(level)
-            k = kernel_matrix(RADIUS_INNER * r * self.s, RADIUS_OUTER * r * self.s)
+            k = self._k(RADIUS_INNER * r * self.s, RADIUS_OUTER * r * self.s)
             self._ops[key] = pinv_truncated(k, self.rcond)
         return self._ops[key]
 
@@ -86,7 +94,7 @@ class KIFMM:
             rp, rc = self._r(child_level - 1), self._r(child_level)
             x = RADIUS_OUTER * rp * self.s
             y = self._child_shift(child_level, octant) + RADIUS_INNER * rc * self.s
-            self._ops[key] = kernel_matrix(x, y)
+            self._ops[key] = self._k(x, y)
         return self._ops[key]
 
     def l2l(self, child_level, octant):
@@ -96,7 +104,7 @@ class KIFMM:
             rp, rc = self._r(child_level - 1), self._r(child_level)
             x = self._child_shift(child_level, octant) + RADIUS_INNER * rc * self.s
             y = RADIUS_OUTER * rp * self.s
-            self._ops[key] = kernel_matrix(x, y)
+            self._ops[key] = self._k(x, y)
         return self._ops[key]
 
     def m2l(self, level, offset):
@@ -107,7 +115,7 @@ class KIFMM:
             r = self._r(level)
             x = RADIUS_INNER * r * self.s
             y = 2.0 * r * np.array(offset, dtype=np.float64) + RADIUS_INNER * r * self.s
-            self._ops[key] = kernel_matrix(x, y)
+            self._ops[key] = self._k(x, y)
         return self._ops[key]
 
     # -- surfaces of a box ---------------------------------------------------
@@ -136,6 +144,8 @@ class KIFMM:
         (n_rhs, 3, n_tgt)).
         """
         t = self.tree
+        if gradient and self.kappa != 0.0:
+            raise ValueError("gradients are defined here for the Laplace kernel only")
         q = np.asarray(charges, dtype=np.float64)
         one = q.ndim == 1
         qm = (q[None, :] if one else q).T          # (n_src, n_rhs)
@@ -163,7 +173,7 @@ class KIFMM:
             for b in t.boxes_at(level):
                 if t.is_leaf(b):
                     s_ids = t.srcs[b]
-                    u = kernel_matrix(self._surf(b, RADIUS_OUTER), t.src[s_ids]) @ qm[s_ids]
+                    u = self._k(self._surf(b, RADIUS_OUTER), t.src[s_ids]) @ qm[s_ids]
                 else:
                     u = np.zeros((self.n, n_rhs))
                     for c in t.children[b]:
@@ -189,7 +199,7 @@ class KIFMM:
                     if x_dc is None:
                         x_dc = self._surf(b, RADIUS_INNER)
                     s_ids = t.srcs[a]
-                    d += kernel_matrix(x_dc, t.src[s_ids]) @ qm[s_ids]
+                    d += self._k(x_dc, t.src[s_ids]) @ qm[s_ids]
                 down[b] = self.dc2e(level) @ d
 
         # Leaves: L2P + M2P (W) + near field (U).
@@ -208,7 +218,7 @@ class KIFMM:
                 terms.append((t.src[s_ids], qm[s_ids]))
             acc = np.zeros((len(ids), n_rhs))
             for y, dens in terms:
-                acc += kernel_matrix(x, y) @ dens
+                acc += self._k(x, y) @ dens
             pot[ids] = acc
             if gradient:
                 for y, dens in terms:
@@ -227,9 +237,9 @@ class KIFMM:
 
 
 def kifmm(src, charges, tgt, p, *, uniform_depth=-1, ncrit=64, max_depth=12,
-          balance=True, center=None, halfwidth=0.0, rcond=1e-9, sample=None):
+          balance=True, center=None, halfwidth=0.0, rcond=1e-9, sample=None, kappa=0.0):
     """Convenience wrapper: build the oracle tree, then evaluate (O2)."""
     tree = Octree(src, tgt, uniform_depth=uniform_depth, ncrit=ncrit,
                   max_depth=max_depth, balance=balance, center=center,
                   halfwidth=halfwidth)
-    return KIFMM(tree, p, rcond).evaluate(charges, sample=sample)
+    return KIFMM(tree, p, rcond, kappa).evaluate(charges, sample=sample)
