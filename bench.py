@@ -85,7 +85,10 @@ def _measured_traffic(precision: str):
 # 1e-5 bound at 1M points (4.6e-6 vs plain FP64; the split-FP16 mode is 4x more
 # accurate and ~4% slower).  The multi-RHS workload, bound 1e-6, uses split FP16.
 DEFAULT_PRECISION = {"uniform_1m": "bf16x3", "plain_20k": "fp64", "sphere_4m": "bf16x3",
-                     "batch_64": "fp32", "multi_rhs_1m": "f16x3", "paper_sphere_1m": "f16x3"}
+                     "batch_64": "fp32", "multi_rhs_1m": "f16x3", "paper_sphere_1m": "f16x3",
+                     "screened_1m": "bf16x3"}
+# the screened (Yukawa) kernel's workload: the 1M cube with kappa = 10 / the domain size
+SCREENED_KAPPA = 10.0
 
 
 def _problems(args):
@@ -103,6 +106,8 @@ def _problems(args):
         return [I.multi_rhs_1m()]
     if args.config == "paper_sphere_1m":
         return [I.paper_sphere_1m()]
+    if args.config == "screened_1m":
+        return [I.uniform_1m()]
     raise SystemExit(f"unknown config {args.config}")
 
 
@@ -140,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="uniform_1m",
-                    choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m",
+                    choices=["uniform_1m", "plain_20k", "sphere_4m", "batch_64", "multi_rhs_1m", "screened_1m",
                              "paper_sphere_1m"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16x3", "bf16x5", "f16x3", "fp64", "fp64+m2l_fp32", "fp64+m2l_f16x3"])
     ap.add_argument("--no-fp64-leg", action="store_true")
@@ -195,7 +200,11 @@ def main():
     # the pseudo-inverses on the GPU from p = 8 on (their host SVD dominates
     # there: 7 s at p = 10); below, the host is as fast
     ops_on_gpu = prob.p >= 8
-    ops = K.Operators(prob.p, device_svd=ops_on_gpu)
+    kappa = SCREENED_KAPPA if args.config == "screened_1m" else 0.0
+    if kappa:
+        ops = K.Operators.screened(prob.p, kappa, trees[0], device_svd=ops_on_gpu)
+    else:
+        ops = K.Operators(prob.p, device_svd=ops_on_gpu)
     t_ops = time.perf_counter() - t0
     tree = trees[0]
     info = tree.info()
@@ -272,7 +281,7 @@ def main():
         result["rel_l2_vs_fp64_gpu"] = rel(res[0], ref[0])
     # direct sum on a seeded sample of targets (first problem, first charge vector)
     idx = I.sample_indices(n, args.direct_sample)
-    exact = direct.direct(prob.points, prob.charges[0], prob.points[idx])
+    exact = direct.direct(prob.points, prob.charges[0], prob.points[idx], kappa=kappa)
     result["rel_l2_vs_direct_sample"] = rel(res[0][0][idx], exact)
     if args.config == "plain_20k":
         from oracle import kifmm as OK
@@ -341,7 +350,7 @@ def main():
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
     roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
 
-    if not batch and n_rhs == 1 and not args.no_gradient:
+    if not batch and n_rhs == 1 and not args.no_gradient and not kappa:
         # potentials + gradients (kifmm_evaluate_gradient), graph replays as
         # above, against the FP64 gradient on the same tree
         def grad_run(prec, steps):
@@ -401,7 +410,8 @@ def main():
         "dtype": {"fp32": "f32", "bf16x3": "f32+bf16x3", "bf16x5": "f32+bf16x5", "f16x3": "f32+f16x3",
                   "fp64": "f64", "fp64+m2l_fp32": "f64+f32", "fp64+m2l_f16x3": "f64+f16x3"}[precision],
         "data": "synthetic",
-        "config": {"workload": prob.name if not batch else f"batch of {len(probs)} problems",
+        "config": {"workload": (prob.name + (f"_screened_kappa{kappa:g}" if kappa else "")) if not batch
+                   else f"batch of {len(probs)} problems",
                    "n_points": n_total, "n_rhs": n_rhs, "p": prob.p,
                    "depth": max(t.info().depth for t in trees),
                    "leaves": sum(t.info().n_leaves for t in trees), "precision": precision},

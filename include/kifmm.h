@@ -170,6 +170,23 @@ kifmm_status kifmm_precompute_operators(int32_t p, double rcond, kifmm_ops** out
 kifmm_status kifmm_precompute_operators_ex(int32_t p, double rcond, int32_t flags,
                                            kifmm_ops** out);
 
+/* Operators of the screened (Yukawa) kernel exp(-kappa r) / (4 pi r),
+ * kappa > 0: the method is kernel independent (its operators are kernel
+ * evaluations on the check and equivalent surfaces and pseudo-inverses of
+ * them; section "Computational structure of FMM operators"), but this kernel
+ * is not homogeneous, so one set of tables is formed per level l = 2 ..
+ * max_level for boxes of half-width root_halfwidth / 2^l (the Laplace
+ * kernel's single reference set does not apply).  The operators serve trees
+ * with exactly that root half-width and depth <= max_level (evaluate returns
+ * EINVAL otherwise); kifmm_evaluate and kifmm_evaluate_batch use the kernel
+ * in every step (the particle kernels evaluate exp(-kappa r) / r); gradients
+ * and the operator cache are Laplace-only (EUNSUPPORTED).  flags as in
+ * kifmm_precompute_operators_ex.  EINVAL for kappa <= 0, root_halfwidth <= 0
+ * or max_level outside [2, 20]. */
+kifmm_status kifmm_precompute_operators_screened(int32_t p, double rcond, double kappa,
+                                                 double root_halfwidth, int32_t max_level,
+                                                 int32_t flags, kifmm_ops** out);
+
 /* Persistent operator cache.  kifmm_ops_save writes every table of `ops`
  * with its key (p, rcond, the surface radii 1.05 / 2.95) and a checksum to
  * `path` (through a temporary file renamed into place).  kifmm_ops_load

@@ -87,9 +87,19 @@ static int64_t max_pairs(int n, int n_rhs) {
   return (int64_t(64) << 30) / (ld * n_rhs * 8);
 }
 // a cached plan is reused only if it was cut the way the tuning asks now
-static bool plan_current(const HostForest& F, int TB, int TBm, int n, int n_rhs) {
+static bool plan_current(const HostForest& F, int TB, int TBm, int n, int n_rhs, bool per_level) {
   return F.dc2e.back().TB == TB && F.m2l.TB == TBm && F.m2l.split == (g_m2l_split.load() != 0) &&
-         F.pair_fill == pair_fill(n) && F.max_pairs == max_pairs(n, n_rhs);
+         F.pair_fill == pair_fill(n) && F.max_pairs == max_pairs(n, n_rhs) && F.per_level == per_level;
+}
+
+// Operators of the screened kernel are tied to a root box size and a depth.
+static void check_kernel(const HostTree& T, const HostOps& O, bool grad) {
+  if (O.kernel == 0) return;
+  if (grad) raise(KIFMM_EUNSUPPORTED, "evaluate_gradient: Laplace-kernel operators only");
+  if (T.r0 != O.r0)
+    raise(KIFMM_EINVAL, "evaluate: screened-kernel operators were precomputed for another root half-width");
+  if (T.depth > O.levels - 1)
+    raise(KIFMM_EINVAL, "evaluate: the tree is deeper than the screened-kernel operators' max_level");
 }
 
 template <class F>
@@ -246,6 +256,21 @@ kifmm_status kifmm_precompute_operators_ex(int32_t p, double rcond, int32_t flag
   });
 }
 
+kifmm_status kifmm_precompute_operators_screened(int32_t p, double rcond, double kappa,
+                                                 double root_halfwidth, int32_t max_level, int32_t flags,
+                                                 kifmm_ops** out) {
+  if (!out) return fail(KIFMM_EINVAL, "precompute_operators_screened: null output handle");
+  if (flags & ~int32_t(KIFMM_PRECOMPUTE_DEVICE_SVD))
+    return fail(KIFMM_EINVAL, "precompute_operators_screened: unknown flag");
+  if (!(kappa > 0.0)) return fail(KIFMM_EINVAL, "precompute_operators_screened: kappa must be > 0");
+  return guard([&] {
+    auto o = std::make_unique<kifmm_ops>();
+    o->host.reset(build_host_ops(p, rcond, (flags & KIFMM_PRECOMPUTE_DEVICE_SVD) != 0, kappa, root_halfwidth,
+                                 max_level));
+    *out = o.release();
+  });
+}
+
 kifmm_status kifmm_ops_save(const kifmm_ops* ops, const char* path) {
   if (!ops) return fail(KIFMM_EINVAL, "ops_save: null ops");
   return guard([&] { save_host_ops(*ops->host, path); });
@@ -296,7 +321,10 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
     auto* t = const_cast<kifmm_tree*>(tree);
     const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
     const int n = ops->host->n;
-    bool rebuild = !t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs);
+    const bool per_level = ops->host->kernel != 0;
+    check_kernel(*t->host, *ops->host, grad);
+    bool rebuild =
+        !t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs, per_level);
     if (t->pending && (rebuild || dev_point_view(*t->state).device != current_device())) {
       // the device-updated points live only in the resident forest: a new
       // forest (new plans, or another device) is built from the host copy
@@ -307,7 +335,7 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
       t->state.reset(new EvalState());
       const HostTree* one = t->host.get();
       t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0,
-                                        pair_fill(n), max_pairs(n, n_rhs)));
+                                        pair_fill(n), max_pairs(n, n_rhs), per_level));
       t->state_n = ops->host->n;
     }
     const void* q[1] = {charges};
@@ -349,13 +377,15 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
       std::lock_guard<std::mutex> lk(g_batch_mu);
       auto& slot = g_batches[key];
       const int n = ops->host->n;
-      if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1), n, 1)) slot.reset();
+      const bool per_level = ops->host->kernel != 0;
+      for (int k = 0; k < n_prob; ++k) check_kernel(*trees[k]->host, *ops->host, false);
+      if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1), n, 1, per_level)) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);
         for (int k = 0; k < n_prob; ++k) hts[k] = &host_of(trees[k]);
         auto s = std::make_unique<EvalState>();
         s->host.reset(build_forest(hts.data(), n_prob, *ops->host, plan_width(1), m2l_plan_width(1),
-                                   g_m2l_split.load() != 0, pair_fill(n), max_pairs(n, 1)));
+                                   g_m2l_split.load() != 0, pair_fill(n), max_pairs(n, 1), per_level));
         slot = std::move(s);
       }
       st = slot.get();

@@ -51,6 +51,10 @@ __device__ inline int f16_density_exp(const unsigned* absmax) {
 
 struct DevOps {
   int n = 0, ld = 0, p = 0;
+  // table sets: 1 (Laplace), or one per level (screened kernel, exp(-kappa d)
+  // / (4 pi d)); every table below holds `levels` sets back to back
+  int levels = 1;
+  double kappa = 0.0;
   double *uc2e = nullptr, *dc2e = nullptr;               // [ld][ld]
   float *m2m32 = nullptr, *l2l32 = nullptr, *m2l32 = nullptr;  // [k][ld][ld]
   double *m2m64 = nullptr, *l2l64 = nullptr, *m2l64 = nullptr;
@@ -341,23 +345,25 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
     O->n = H.n;
     O->p = H.p;
     O->ld = round32(H.n);
-    O->uc2e = dev_upload<double>(O->allocs, pad_table<double>(H.uc2e, 1, H.n, O->ld));
-    O->dc2e = dev_upload<double>(O->allocs, pad_table<double>(H.dc2e, 1, H.n, O->ld));
+    O->levels = H.levels;
+    O->kappa = H.kappa;
+    O->uc2e = dev_upload<double>(O->allocs, pad_table<double>(H.uc2e, H.levels, H.n, O->ld));
+    O->dc2e = dev_upload<double>(O->allocs, pad_table<double>(H.dc2e, H.levels, H.n, O->ld));
     std::vector<double> s4(4 * size_t(H.n), 0.0);
     for (int i = 0; i < H.n; ++i)
       for (int d = 0; d < 3; ++d) s4[4 * i + d] = H.surf[3 * i + d];
     O->surf = dev_upload<double4>(O->allocs, s4);
   }
   if (need.bulk64 && !O->m2m64) {
-    O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8, H.n, O->ld));
-    O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8, H.n, O->ld));
+    O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8 * H.levels, H.n, O->ld));
+    O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8 * H.levels, H.n, O->ld));
   }
   if (!need.bulk64 && !O->m2m32) {
-    O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8, H.n, O->ld));
-    O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8, H.n, O->ld));
+    O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8 * H.levels, H.n, O->ld));
+    O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8 * H.levels, H.n, O->ld));
   }
   if (need.m2l64 && !O->m2l64)
-    O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
+    O->m2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2l, kNumM2L * H.levels, H.n, O->ld));
   if (need.check_form) {
     if ((need.f16 && !O->m2lc_h) || (need.m2l32 && !O->m2lc32)) {
       std::vector<double> pad = pad_table<double>(m2l_check_form_device(H), kNumM2L, H.n, O->ld);
@@ -369,11 +375,12 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
     }
   } else {
     if (need.m2l32 && !O->m2l32)
-      O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L, H.n, O->ld));
-    if (need.f16 && !O->m2l_h) O->m2l_h = upload_split16(O, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld));
+      O->m2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2l, kNumM2L * H.levels, H.n, O->ld));
+    if (need.f16 && !O->m2l_h)
+      O->m2l_h = upload_split16(O, pad_table<double>(H.m2l, kNumM2L * H.levels, H.n, O->ld));
   }
   if (need.bf16 && !O->m2l_b)
-    O->m2l_b = upload_split(O, pad_table<double>(H.m2l, kNumM2L, H.n, O->ld),
+    O->m2l_b = upload_split(O, pad_table<double>(H.m2l, kNumM2L * H.levels, H.n, O->ld),
                             [](double x, uint16_t& hi, uint16_t& lo) {
                               hi = bf16_bits(float(x));
                               lo = bf16_bits(float(x - bf16_value(hi)));
@@ -699,6 +706,7 @@ struct P2PArgs {
   const int32_t* l2_off;
   const int32_t* l2_items;
   int grad;  // leaf kernel: also the gradient (pot holds [n_rhs][4][ntgt])
+  double kappa;  // screened kernel exp(-kappa d) / (4 pi d); 0: Laplace
 };
 
 template <class T, int RC, bool LO = false>
@@ -770,11 +778,14 @@ __device__ inline void segment_info(const P2PArgs<T>& a, int wi, int B, int4 gB,
 // Accumulates the sources of segments [s0, s1) into acc, computing pair terms
 // in precision U (staging in LDS, FP32/FP64 partials folded into FP64).  With
 // GRAD (one right-hand side), gacc also sums q (x - y) / |x - y|^3 per axis.
-template <class U, class T, int MODE, int RC, int TCH, bool GRAD = false>
+template <class U, class T, int MODE, int RC, int TCH, bool GRAD = false, bool SCR = false>
 __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st, int wi, int B,
                           int4 gB, int nU, int s0, int s1, int rhs0, const double (&tx)[kNch],
                           const double (&ty)[kNch], const double (&tz)[kNch], int nchunks,
-                          double (&acc)[kNch][RC], double (&gacc)[kNch][3]) {
+                          double (&acc)[kNch][RC], double (&gacc)[kNch][3], double kB) {
+  // SCR: the screened kernel, exp(-kB d) / d in the target box's units
+  // (kB = kappa r_B); its factor multiplies 1 / d
+  const U ukB = U(kB);
   static_assert(!GRAD || RC == 1, "gradients are summed for one right-hand side per block");
   // Gradient terms cancel strongly between neighbours (points on a surface):
   // in FP32 the differences x - y then take the positions as two-float sums
@@ -912,6 +923,10 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
             U ri;
             if constexpr (decltype(checked)::value) ri = rinv(r2);   // coincident pair -> 0
             else ri = rinv_nonzero(r2);
+            if constexpr (SCR) {
+              if constexpr (sizeof(U) == 4) ri *= __expf(-ukB * (r2 * ri));
+              else ri *= exp(-ukB * (r2 * ri));
+            }
             if constexpr (RC == 1) {
               part[0] += s.w * ri;
               if constexpr (GRAD) {
@@ -983,7 +998,7 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 // groups stride over the staged sources, then reduce in FP64.  Particle
 // segments are computed in T, equivalent-surface segments (L2P, M2P) in TF:
 // FP64 at high order, where the equivalent densities cancel strongly.
-template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false>
+template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false, bool SCR = false>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
   constexpr int NT = 256, SL = NT / TCH;
   static_assert(!GRAD || (MODE == MODE_LEAF && RC == 1), "gradients: leaf kernel, one right-hand side");
@@ -1051,12 +1066,13 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       for (int k = 0; k < 3; ++k) gacc[c][k] = 0.0;
     }
     const int nchunks = (min(nt - t0, TCH * kNch) + TCH - 1) / TCH;
+    const double kB = SCR ? a.kappa * a.box_r[B] : 0.0;
     if (MODE != MODE_FAR)
-      p2p_phase<T, T, MODE, RC, TCH, GRAD>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz, nchunks,
-                                           acc, gacc);
+      p2p_phase<T, T, MODE, RC, TCH, GRAD, SCR>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz,
+                                                nchunks, acc, gacc, kB);
     if (MODE != MODE_NEAR && nseg > nnear)
-      p2p_phase<TF, T, MODE, RC, TCH, GRAD>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz,
-                                            nchunks, acc, gacc);
+      p2p_phase<TF, T, MODE, RC, TCH, GRAD, SCR>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz,
+                                                 nchunks, acc, gacc, kB);
 
     // reduce the slices of each chunk and write
     const double rB = a.box_r[B];
@@ -1752,11 +1768,11 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   ps.launches++;
 }
 
-template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false>
+template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false, bool SCR = false>
 static void run_p2p(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s, PhaseScope& ps) {
   if (nwork == 0) return;
   dim3 grid(nwork, (n_rhs + RC - 1) / RC);
-  hipLaunchKernelGGL((p2p_kernel<T, TF, MODE, RC, TCH, GRAD>), grid, dim3(256), 0, s, args);
+  hipLaunchKernelGGL((p2p_kernel<T, TF, MODE, RC, TCH, GRAD, SCR>), grid, dim3(256), 0, s, args);
   LAUNCHCHECK("p2p_kernel");
   ps.launches++;
 }
@@ -1768,24 +1784,31 @@ static void run_p2p(const P2PArgs<T>& args, int nwork, int n_rhs, hipStream_t s,
 static int g_far_fp64_min_p = 10;
 void set_far_fp64_min_p(int p) { g_far_fp64_min_p = p; }
 
+template <class T, int MODE, int TCH, bool SCR>
+static void run_p2p_rhs(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64, hipStream_t s,
+                        PhaseScope& ps) {
+  if (far64) {
+    if (n_rhs == 1) run_p2p<T, double, MODE, 1, TCH, false, SCR>(args, nwork, n_rhs, s, ps);
+    else run_p2p<T, double, MODE, 8, TCH, false, SCR>(args, nwork, n_rhs, s, ps);
+  } else {
+    if (n_rhs == 1) run_p2p<T, T, MODE, 1, TCH, false, SCR>(args, nwork, n_rhs, s, ps);
+    else run_p2p<T, T, MODE, 8, TCH, false, SCR>(args, nwork, n_rhs, s, ps);
+  }
+}
+
 template <class T, int MODE, int TCH>
 static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64, hipStream_t s,
                        PhaseScope& ps) {
   if constexpr (MODE == MODE_LEAF) {
     if (args.grad) {
-      // potential and gradient: one right-hand side per block
+      // potential and gradient (Laplace kernel): one right-hand side per block
       if (far64) run_p2p<T, double, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
       else run_p2p<T, T, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
       return;
     }
   }
-  if (far64) {
-    if (n_rhs == 1) run_p2p<T, double, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
-    else run_p2p<T, double, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
-  } else {
-    if (n_rhs == 1) run_p2p<T, T, MODE, 1, TCH>(args, nwork, n_rhs, s, ps);
-    else run_p2p<T, T, MODE, 8, TCH>(args, nwork, n_rhs, s, ps);
-  }
+  if (args.kappa != 0.0) run_p2p_rhs<T, MODE, TCH, true>(args, nwork, n_rhs, far64, s, ps);
+  else run_p2p_rhs<T, MODE, TCH, false>(args, nwork, n_rhs, far64, s, ps);
 }
 
 // Where the near field forks off the evaluation stream: 0 right after the
@@ -1838,6 +1861,10 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     m2m = O.m2m32;
     l2l = O.l2l32;
   }
+  // the operator set of level l (one set for the Laplace kernel)
+  if (O.levels > 1 && F.depth > O.levels - 1)
+    raise(KIFMM_EINVAL, "evaluate: the forest is deeper than the operators' levels");
+  auto set = [&](int l) { return int64_t(O.levels > 1 ? l : 0); };
 
   {
     PhaseScope ps(PH_GATHER, s);
@@ -1870,6 +1897,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   base.pot = W.pot;
   base.ntgt = F.ntgt;
   base.grad = grad ? 1 : 0;
+  base.kappa = O.kappa;
   // The near field needs only the gathered charges; it runs on the
   // auxiliary stream, forked after the gather (g_near_fork 0), after P2M (2),
   // before M2L (1) or after it (3), and is joined before the far field.  With
@@ -1907,7 +1935,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
       PhaseScope ps(PH_M2M, s);
       // per-child contributions into the (not yet used) downward check
       // columns, then the per-parent sums into the upward check potentials
-      run_gemm<GF, T, T>(F.m2m[l], m2m, nn, ld, F.nbox, n_rhs, up_eq, dn_chk, false, s, ps);
+      run_gemm<GF, T, T>(F.m2m[l], m2m + set(l) * 8 * nn, nn, ld, F.nbox, n_rhs, up_eq, dn_chk, false, s, ps);
       const int npar = F.n_m2m_sum[l];
       if (npar > 0) {
         const int64_t upb = int64_t(n_rhs) * ld * int64_t(sizeof(T)) / 16;
@@ -1921,7 +1949,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     }
     {
       PhaseScope ps(PH_UC2E, s);
-      run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e, 0, ld, F.nbox, n_rhs, up_chk, up_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.uc2e[l], O.uc2e + set(l) * nn, 0, ld, F.nbox, n_rhs, up_chk, up_eq, false, s, ps);
     }
   }
   if (near_fork == 1) fork_near();
@@ -2036,11 +2064,11 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
   for (int l = 2; l <= F.depth; ++l) {
     if (l >= 3) {
       PhaseScope ps(PH_L2L, s);
-      run_gemm<GF, T, T>(F.l2l[l], l2l, nn, ld, F.nbox, n_rhs, dn_eq, dn_chk, true, s, ps);
+      run_gemm<GF, T, T>(F.l2l[l], l2l + set(l) * 8 * nn, nn, ld, F.nbox, n_rhs, dn_eq, dn_chk, true, s, ps);
     }
     {
       PhaseScope ps(PH_DC2E, s);
-      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e, 0, ld, F.nbox, n_rhs, dn_chk, dn_eq, false, s, ps);
+      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e + set(l) * nn, 0, ld, F.nbox, n_rhs, dn_chk, dn_eq, false, s, ps);
     }
   }
   {
@@ -2097,10 +2125,12 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   need.bf16 = prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5;
   need.f16 = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3;
   // folded check form for the FP32 / FP16 M2L operands at high order
-  need.check_form = (need.m2l32 || need.f16) && hops.p >= g_m2l_check_min_p;
+  need.check_form = (need.m2l32 || need.f16) && hops.p >= g_m2l_check_min_p && hops.kernel == 0;
   DevOps* O = ops_for_device(oc, hops, dev, need);
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");
+  if ((hops.kernel != 0) != st.host->per_level)
+    raise(KIFMM_EINVAL, "evaluate: the cached plans were built for another kernel");
   DevWork* W = work_for(F, fp64, n_rhs, grad);
   if (need.bf16 || need.f16) ensure_split(F, W);
   ensure_pairs(F, W);

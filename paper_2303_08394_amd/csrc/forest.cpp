@@ -53,7 +53,7 @@ Plan new_plan(int TB) {
 }  // namespace
 
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
-                         bool split, double pair_fill, int64_t max_pairs) {
+                         bool split, double pair_fill, int64_t max_pairs, bool per_level) {
   auto* Fp = new HostForest();
   HostForest& F = *Fp;
   F.nprob = n;
@@ -339,12 +339,20 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       for (int o = 0; o < 8; ++o)
         if (pos[o] < q[o].size()) {
           Part& t = q[o][pos[o]++];
-          add_tile(F.m2l, t.cols, t.opl, t.srcs);
+          if (per_level) {
+            const int32_t lev_off = F.box_geo[4 * size_t(t.cols[0]) + 3] * kNumM2L;
+            std::vector<int32_t> ops(t.opl);
+            for (auto& v : ops) v += lev_off;
+            add_tile(F.m2l, t.cols, ops, t.srcs);
+          } else {
+            add_tile(F.m2l, t.cols, t.opl, t.srcs);
+          }
           any = true;
         }
     }
     F.m2l.atomic = true;
     F.m2l.split = split;
+    F.per_level = per_level;
 
     // Pair-by-pair M2L of the sparse problems: pairs sorted by offset, then
     // target; tiles of TBm pairs of one offset (one step each); pair p writes
@@ -367,9 +375,13 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
     F.n_pairs = int64_t(pe.size());
     if (F.n_pairs > (int64_t(1) << 31) - 1) raise(KIFMM_EUNSUPPORTED, "forest: too many M2L pairs");
     std::vector<std::vector<std::pair<int32_t, int32_t>>> per_op(kNumM2L);  // tile ranges in pe
+    auto level_of = [&](int32_t g) { return F.box_geo[4 * size_t(g) + 3]; };
     for (size_t i = 0; i < pe.size();) {
       size_t j = i;
-      while (j < pe.size() && pe[j].op == pe[i].op && j - i < size_t(TBm)) ++j;
+      // (with operators per level a tile also keeps to one level)
+      while (j < pe.size() && pe[j].op == pe[i].op && j - i < size_t(TBm) &&
+             (!per_level || level_of(pe[j].t) == level_of(pe[i].t)))
+        ++j;
       per_op[pe[i].op].push_back({int32_t(i), int32_t(j)});
       i = j;
     }
@@ -396,7 +408,8 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
             cols.push_back(i);
             srcs.push_back(pe[i].s);
           }
-          add_tile(F.m2l_pair, cols, {pe[r.first].op}, {srcs});
+          const int32_t op = pe[r.first].op + (per_level ? level_of(pe[r.first].t) * kNumM2L : 0);
+          add_tile(F.m2l_pair, cols, {op}, {srcs});
           any = true;
         }
     }

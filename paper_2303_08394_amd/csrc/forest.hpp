@@ -71,6 +71,9 @@ struct HostForest {
   int64_t n_pairs = 0;
   double pair_fill = 0.0;          // the threshold the plans were built for
   int64_t max_pairs = 0;           // and the pair count cap
+  // M2L operator indices include the level (level * 316 + offset): operator
+  // tables per level, as the screened kernel needs
+  bool per_level = false;
   // statistics of the lists (for work counts)
   int64_t n_u_pairs = 0, n_v_pairs = 0, n_w_pairs = 0, n_x_pairs = 0;
   int64_t p2p_interactions = 0;  // sum over U pairs of n_tgt(B) * n_src(A)
@@ -80,8 +83,9 @@ struct HostForest {
 // per tile for M2M, L2L and the solves, TBm for M2L.  With split, every M2L
 // tile is run as two blocks (even and odd x offsets).  Problems whose M2L
 // tiles fill less than pair_fill of their slots run M2L pair by pair, unless
-// that makes more than max_pairs pairs (then none does).
+// that makes more than max_pairs pairs (then none does).  per_level: M2L
+// operator indices carry the target level (tables per level).
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
-                         bool split, double pair_fill, int64_t max_pairs);
+                         bool split, double pair_fill, int64_t max_pairs, bool per_level = false);
 
 }  // namespace kifmm

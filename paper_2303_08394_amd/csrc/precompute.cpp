@@ -36,15 +36,19 @@ static std::vector<double> surface_points(int p) {
 }
 
 // K[i][j] = 1/(4 pi |x_i - y_j|) for x_i = xs + xr * s_i, y_j = ys + yr * s_j.
+// out[i][j] = G(x_i, y_j), x_i = xs + xr s_i, y_j = ys + yr s_j, for the
+// Laplace kernel 1 / (4 pi d) (lambda = 0) or the screened kernel
+// exp(-lambda d) / (4 pi d) in box units (lambda = kappa times the box size).
 static void kernel_block(const std::vector<double>& s, int n, const double xs[3], double xr,
-                         const double ys[3], double yr, double* out) {
+                         const double ys[3], double yr, double* out, double lambda = 0.0) {
   for (int i = 0; i < n; ++i) {
     double x0 = xs[0] + xr * s[3 * i], x1 = xs[1] + xr * s[3 * i + 1], x2 = xs[2] + xr * s[3 * i + 2];
     for (int j = 0; j < n; ++j) {
       double d0 = x0 - (ys[0] + yr * s[3 * j]);
       double d1 = x1 - (ys[1] + yr * s[3 * j + 1]);
       double d2 = x2 - (ys[2] + yr * s[3 * j + 2]);
-      out[size_t(i) * n + j] = kInv4Pi / std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double d = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      out[size_t(i) * n + j] = lambda == 0.0 ? kInv4Pi / d : kInv4Pi * std::exp(-lambda * d) / d;
     }
   }
 }
@@ -134,54 +138,78 @@ std::vector<double> pinv_truncated(const double* a, int n, double rcond, int* ra
   return P;
 }
 
-HostOps* build_host_ops(int p, double rcond, bool device_svd) {
+HostOps* build_host_ops(int p, double rcond, bool device_svd, double kappa, double r0, int max_level) {
   if (p < 2 || p > 16) raise(KIFMM_EINVAL, "precompute_operators: p must be in [2, 16]");
   if (!(rcond > 0.0 && rcond < 1.0)) raise(KIFMM_EINVAL, "precompute_operators: rcond must be in (0, 1)");
+  const bool screened = kappa != 0.0;
+  if (screened) {
+    if (!(kappa > 0.0) || !std::isfinite(kappa)) raise(KIFMM_EINVAL, "precompute_operators: kappa must be > 0");
+    if (!(r0 > 0.0) || !std::isfinite(r0)) raise(KIFMM_EINVAL, "precompute_operators: root half-width must be > 0");
+    if (max_level < 2 || max_level > 20) raise(KIFMM_EINVAL, "precompute_operators: max_level must be in [2, 20]");
+  }
   auto* O = new HostOps();
   try {
     O->p = p;
     O->rcond = rcond;
+    O->device_svd = device_svd;
+    O->kernel = screened ? 1 : 0;
+    O->kappa = kappa;
+    O->r0 = screened ? r0 : 0.0;
+    O->levels = screened ? max_level + 1 : 1;
     O->surf = surface_points(p);
     const int n = O->n = static_cast<int>(O->surf.size() / 3);
     const size_t nn = size_t(n) * n;
+    const int L = O->levels;
     const double zero[3] = {0, 0, 0};
     std::vector<double> k(nn);
-    // UC2E: upward check (outer) <- upward equivalent (inner)
-    kernel_block(O->surf, n, zero, kRadiusOuter, zero, kRadiusInner, k.data());
-    O->device_svd = device_svd;
     auto pinv = [&](const double* a) {
       return device_svd ? pinv_truncated_device(a, n, rcond) : pinv_truncated(a, n, rcond);
     };
-    O->uc2e = pinv(k.data());
-    // DC2E: downward check (inner) <- downward equivalent (outer)
-    kernel_block(O->surf, n, zero, kRadiusInner, zero, kRadiusOuter, k.data());
-    O->dc2e = pinv(k.data());
-    O->m2m.resize(8 * nn);
-    O->l2l.resize(8 * nn);
-    for (int o = 0; o < 8; ++o) {
-      // child centre relative to the parent, in parent half-widths: +-1/2
-      double sh[3] = {(((o >> 2) & 1) ? 0.5 : -0.5), (((o >> 1) & 1) ? 0.5 : -0.5),
-                      ((o & 1) ? 0.5 : -0.5)};
-      kernel_block(O->surf, n, zero, kRadiusOuter, sh, 0.5 * kRadiusInner, &O->m2m[o * nn]);
-      // parent centre relative to the child, in child half-widths: -+1
-      double ps[3] = {-2 * sh[0], -2 * sh[1], -2 * sh[2]};
-      kernel_block(O->surf, n, zero, kRadiusInner, ps, 2.0 * kRadiusOuter, &O->l2l[o * nn]);
-    }
+    O->uc2e.assign(L * nn, 0.0);
+    O->dc2e.assign(L * nn, 0.0);
+    O->m2m.assign(8 * L * nn, 0.0);
+    O->l2l.assign(8 * L * nn, 0.0);
+    O->m2l.assign(size_t(kNumM2L) * L * nn, 0.0);
     std::fill(std::begin(O->m2l_index), std::end(O->m2l_index), -1);
-    O->m2l.resize(size_t(kNumM2L) * nn);
-    int idx = 0;
     for (int dx = -3; dx <= 3; ++dx)
       for (int dy = -3; dy <= 3; ++dy)
         for (int dz = -3; dz <= 3; ++dz) {
           if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+          O->m2l_index[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)] = int32_t(O->m2l_offset.size() / 3);
           O->m2l_offset.push_back(dx);
           O->m2l_offset.push_back(dy);
           O->m2l_offset.push_back(dz);
-          O->m2l_index[(dx + 3) * 49 + (dy + 3) * 7 + (dz + 3)] = idx;
-          double sh[3] = {2.0 * dx, 2.0 * dy, 2.0 * dz};
-          kernel_block(O->surf, n, zero, kRadiusInner, sh, kRadiusInner, &O->m2l[size_t(idx) * nn]);
-          ++idx;
         }
+    // Table set t: one set for the Laplace kernel (level independent with
+    // scaled check potentials); for the screened kernel one per level l >= 2,
+    // with lambda = kappa r_l in the level's box units (levels 0, 1 unused).
+    for (int t = screened ? 2 : 0; t < L; ++t) {
+      const double lam = screened ? kappa * (r0 / double(int64_t(1) << t)) : 0.0;
+      // UC2E: upward check (outer) <- upward equivalent (inner)
+      kernel_block(O->surf, n, zero, kRadiusOuter, zero, kRadiusInner, k.data(), lam);
+      std::vector<double> u = pinv(k.data());
+      std::copy(u.begin(), u.end(), O->uc2e.begin() + t * nn);
+      // DC2E: downward check (inner) <- downward equivalent (outer)
+      kernel_block(O->surf, n, zero, kRadiusInner, zero, kRadiusOuter, k.data(), lam);
+      u = pinv(k.data());
+      std::copy(u.begin(), u.end(), O->dc2e.begin() + t * nn);
+      for (int o = 0; o < 8; ++o) {
+        // M2M in the parent's units (parent at level t), L2L in the child's
+        // (child at level t): child centre relative to the parent +-1/2
+        double sh[3] = {(((o >> 2) & 1) ? 0.5 : -0.5), (((o >> 1) & 1) ? 0.5 : -0.5),
+                        ((o & 1) ? 0.5 : -0.5)};
+        kernel_block(O->surf, n, zero, kRadiusOuter, sh, 0.5 * kRadiusInner, &O->m2m[(size_t(t) * 8 + o) * nn], lam);
+        // parent centre relative to the child, in child half-widths: -+1
+        double ps[3] = {-2 * sh[0], -2 * sh[1], -2 * sh[2]};
+        kernel_block(O->surf, n, zero, kRadiusInner, ps, 2.0 * kRadiusOuter, &O->l2l[(size_t(t) * 8 + o) * nn], lam);
+      }
+      for (int idx = 0; idx < kNumM2L; ++idx) {
+        const int32_t* d = &O->m2l_offset[3 * size_t(idx)];
+        double sh[3] = {2.0 * d[0], 2.0 * d[1], 2.0 * d[2]};
+        kernel_block(O->surf, n, zero, kRadiusInner, sh, kRadiusInner,
+                     &O->m2l[(size_t(t) * kNumM2L + idx) * nn], lam);
+      }
+    }
   } catch (...) {
     delete O;
     throw;
@@ -214,6 +242,7 @@ struct Fnv {
 
 void save_host_ops(const HostOps& O, const char* path) {
   if (!path) raise(KIFMM_EINVAL, "ops_save: null path");
+  if (O.kernel != 0) raise(KIFMM_EUNSUPPORTED, "ops_save: the cache holds Laplace-kernel operators only");
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = std::fopen(tmp.c_str(), "wb");
   if (!f) raise(KIFMM_EINVAL, std::string("ops_save: cannot write ") + tmp);

@@ -29,11 +29,21 @@ struct HostOps {
   std::vector<int32_t> m2l_offset;  // [316][3] source anchor - target anchor
   int32_t m2l_index[343];           // (dx+3)*49 + (dy+3)*7 + (dz+3) -> op, or -1
   bool device_svd = false;          // pseudo-inverses from the GPU SVD
+  // Kernel: 0 Laplace (one table set); 1 screened, exp(-kappa d) / (4 pi d):
+  // not homogeneous, so one table set per level l (index l, stacked in every
+  // table above: uc2e [levels][n][n], m2m [levels][8][n][n], m2l
+  // [levels][316][n][n]), for boxes of half-width r0 / 2^l; sets 0 and 1 are
+  // zero (unused).
+  int kernel = 0;
+  double kappa = 0.0, r0 = 0.0;
+  int levels = 1;
 };
 
 // device_svd: the two pseudo-inverses on the GPU (pinv_truncated_device);
-// everything else on the host.
-HostOps* build_host_ops(int p, double rcond, bool device_svd = false);
+// everything else on the host.  kappa > 0: the screened kernel, tables for
+// levels 2..max_level of a tree whose root half-width is r0.
+HostOps* build_host_ops(int p, double rcond, bool device_svd = false, double kappa = 0.0, double r0 = 0.0,
+                        int max_level = 0);
 
 // Persistent operator cache: a binary file holding every table of a HostOps
 // with its key (p, rcond, the surface radii) and an FNV-1a checksum.

@@ -44,7 +44,8 @@ _lib = None
 EXPORTED = [
     "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
-    "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_ops_save", "kifmm_ops_load",
+    "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_precompute_operators_screened",
+    "kifmm_ops_save", "kifmm_ops_load",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
@@ -69,6 +70,8 @@ def lib():
     L.kifmm_tree_update_points.argtypes = [P, P, P, P]
     L.kifmm_precompute_operators.argtypes = [I32, C.c_double, C.POINTER(P)]
     L.kifmm_precompute_operators_ex.argtypes = [I32, C.c_double, I32, C.POINTER(P)]
+    L.kifmm_precompute_operators_screened.argtypes = [I32, C.c_double, C.c_double, C.c_double, I32, I32,
+                                                      C.POINTER(P)]
     L.kifmm_ops_save.argtypes = [P, C.c_char_p]
     L.kifmm_ops_load.argtypes = [C.c_char_p, I32, C.c_double, C.POINTER(P)]
     L.kifmm_ops_export.argtypes = [P, I32, D, I64]
@@ -205,6 +208,21 @@ class Operators:
     def save(self, path: str):
         """Writes the operator cache file (kifmm_ops_save)."""
         _check(lib().kifmm_ops_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def screened(cls, p: int, kappa: float, tree, rcond: float = 1e-9, device_svd: bool = False,
+                 max_level=None) -> "Operators":
+        """Operators of the screened kernel exp(-kappa r) / (4 pi r) for trees
+        with the root box of `tree` and at most max_level levels (default: the
+        tree's depth) (kifmm_precompute_operators_screened)."""
+        inf = tree.info()
+        lev = inf.depth if max_level is None else max_level
+        h = C.c_void_p()
+        _check(lib().kifmm_precompute_operators_screened(p, rcond, float(kappa), inf.root_halfwidth,
+                                                         max(2, lev), 1 if device_svd else 0, C.byref(h)))
+        ops = cls(p, rcond, _handle=h)
+        ops.kappa = float(kappa)
+        return ops
 
     @classmethod
     def load(cls, path: str, p: int, rcond: float = 1e-9) -> "Operators":
