@@ -60,21 +60,26 @@ def direct(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
     return out[0] if one else out
 
 
-def gradient_matrices(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+def gradient_matrices(x: np.ndarray, y: np.ndarray, kappa: float = 0.0) -> np.ndarray:
     """G[c, i, j] = d/dx_c of 1 / (4 pi |x_i - y_j|) = -(x_i - y_j)_c / (4 pi |x_i - y_j|^3),
-    and 0 where x_i == y_j.  Returns (3, m, n) float64."""
+    and 0 where x_i == y_j.  With kappa > 0, of the screened kernel
+    exp(-kappa r) / (4 pi r): -(1 + kappa r) exp(-kappa r) (x_i - y_j)_c / (4 pi r^3).
+    Returns (3, m, n) float64."""
     x = np.asarray(x, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     d = x[None, :, :].transpose(2, 1, 0) - y[None, :, :].transpose(2, 0, 1)  # (3, m, n)
     r2 = (d * d).sum(axis=0)
     with np.errstate(divide="ignore", invalid="ignore"):
-        w = -INV_4PI / (r2 * np.sqrt(r2))
+        r = np.sqrt(r2)
+        w = -INV_4PI / (r2 * r)
+        if kappa != 0.0:
+            w = w * (1.0 + kappa * r) * np.exp(-kappa * r)
     w[r2 == 0.0] = 0.0
     return d * w[None]
 
 
 def direct_gradient(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
-                    chunk: int = 1024) -> np.ndarray:
+                    chunk: int = 1024, kappa: float = 0.0) -> np.ndarray:
     """Gradients of the potential at tgt, by the O(N^2) sum (derivative of Eq. 1).
 
     charges (n_src,) or (n_rhs, n_src).  Returns (3, n_tgt) or
@@ -85,7 +90,7 @@ def direct_gradient(src: np.ndarray, charges: np.ndarray, tgt: np.ndarray,
     q2 = q[None, :] if one else q
     out = np.zeros((q2.shape[0], 3, len(tgt)))
     for s in range(0, len(tgt), chunk):
-        g = gradient_matrices(tgt[s:s + chunk], src)
+        g = gradient_matrices(tgt[s:s + chunk], src, kappa)
         for c in range(3):
             out[:, c, s:s + chunk] = (g[c] @ q2.T).T
     return out[0] if one else out

@@ -144,8 +144,6 @@ class KIFMM:
         (n_rhs, 3, n_tgt)).
         """
         t = self.tree
-        if gradient and self.kappa != 0.0:
-            raise ValueError("gradients are defined here for the Laplace kernel only")
         q = np.asarray(charges, dtype=np.float64)
         one = q.ndim == 1
         qm = (q[None, :] if one else q).T          # (n_src, n_rhs)
@@ -222,7 +220,7 @@ class KIFMM:
             pot[ids] = acc
             if gradient:
                 for y, dens in terms:
-                    g = gradient_matrices(x, y)
+                    g = gradient_matrices(x, y, self.kappa)
                     for c in range(3):
                         grad[c, ids] += g[c] @ dens
         out = pot.T

@@ -62,3 +62,22 @@ def test_kifmm_adaptive():
     tree = Octree(x, x, ncrit=24, max_depth=10, **CUBE)
     got = OK.KIFMM(tree, 6, kappa=5.0).evaluate(q[0])
     assert rel(got, direct.direct(x, q[0], x, kappa=5.0)) < 5e-6  # measured 9.1e-7
+
+
+def test_screened_gradient():
+    """Gradient of the screened potential: central differences of the direct
+    screened potential, and the KIFMM gradient against the direct one."""
+    rng = np.random.default_rng(9)
+    src, q = rng.random((300, 3)), rng.uniform(-1, 1, 300)
+    tgt = rng.random((40, 3)) + np.array([2.0, 0.0, 0.0])
+    kappa, h = 3.0, 1e-5
+    g = direct.direct_gradient(src, q, tgt, kappa=kappa)
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (direct.direct(src, q, tgt + e, kappa=kappa) - direct.direct(src, q, tgt - e, kappa=kappa)) / (2 * h)
+        assert rel(g[c], fd) < 1e-7
+    x, qq = I.uniform_cube(3000, seed=1, charge_range=(-1, 1))
+    tree = Octree(x, x, uniform_depth=3, **CUBE)
+    pot, grad = OK.KIFMM(tree, 6, kappa=5.0).evaluate(qq[0], gradient=True)
+    assert rel(grad, direct.direct_gradient(x, qq[0], x, kappa=5.0)) < 5e-5
