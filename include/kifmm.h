@@ -179,8 +179,9 @@ kifmm_status kifmm_precompute_operators_ex(int32_t p, double rcond, int32_t flag
  * kernel's single reference set does not apply).  The operators serve trees
  * with exactly that root half-width and depth <= max_level (evaluate returns
  * EINVAL otherwise); kifmm_evaluate and kifmm_evaluate_batch use the kernel
- * in every step (the particle kernels evaluate exp(-kappa r) / r); gradients
- * and the operator cache are Laplace-only (EUNSUPPORTED).  flags as in
+ * in every step (the particle kernels evaluate exp(-kappa r) / r), and so
+ * does kifmm_evaluate_gradient (-(1 + kappa r) exp(-kappa r) (x - y) / r^3);
+ * the operator cache is Laplace-only (EUNSUPPORTED).  flags as in
  * kifmm_precompute_operators_ex.  EINVAL for kappa <= 0, root_halfwidth <= 0
  * or max_level outside [2, 20]. */
 kifmm_status kifmm_precompute_operators_screened(int32_t p, double rcond, double kappa,

@@ -93,9 +93,8 @@ static bool plan_current(const HostForest& F, int TB, int TBm, int n, int n_rhs,
 }
 
 // Operators of the screened kernel are tied to a root box size and a depth.
-static void check_kernel(const HostTree& T, const HostOps& O, bool grad) {
+static void check_kernel(const HostTree& T, const HostOps& O) {
   if (O.kernel == 0) return;
-  if (grad) raise(KIFMM_EUNSUPPORTED, "evaluate_gradient: Laplace-kernel operators only");
   if (T.r0 != O.r0)
     raise(KIFMM_EINVAL, "evaluate: screened-kernel operators were precomputed for another root half-width");
   if (T.depth > O.levels - 1)
@@ -322,7 +321,7 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
     const int TB = plan_width(n_rhs), TBm = m2l_plan_width(n_rhs);
     const int n = ops->host->n;
     const bool per_level = ops->host->kernel != 0;
-    check_kernel(*t->host, *ops->host, grad);
+    check_kernel(*t->host, *ops->host);
     bool rebuild =
         !t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs, per_level);
     if (t->pending && (rebuild || dev_point_view(*t->state).device != current_device())) {
@@ -378,7 +377,7 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
       auto& slot = g_batches[key];
       const int n = ops->host->n;
       const bool per_level = ops->host->kernel != 0;
-      for (int k = 0; k < n_prob; ++k) check_kernel(*trees[k]->host, *ops->host, false);
+      for (int k = 0; k < n_prob; ++k) check_kernel(*trees[k]->host, *ops->host);
       if (slot && !plan_current(*slot->host, plan_width(1), m2l_plan_width(1), n, 1, per_level)) slot.reset();
       if (!slot) {
         std::vector<const HostTree*> hts(n_prob);

@@ -923,14 +923,21 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
             U ri;
             if constexpr (decltype(checked)::value) ri = rinv(r2);   // coincident pair -> 0
             else ri = rinv_nonzero(r2);
+            // gradient factor: 1/d^3, screened (1 + kB d) exp(-kB d) / d^3
+            U gf = U(0);
+            if constexpr (GRAD) gf = ri * ri;
             if constexpr (SCR) {
-              if constexpr (sizeof(U) == 4) ri *= __expf(-ukB * (r2 * ri));
-              else ri *= exp(-ukB * (r2 * ri));
+              const U kd = ukB * (r2 * ri);
+              U e;
+              if constexpr (sizeof(U) == 4) e = __expf(-kd);
+              else e = exp(-kd);
+              ri *= e;
+              if constexpr (GRAD) gf *= U(1) + kd;
             }
             if constexpr (RC == 1) {
               part[0] += s.w * ri;
               if constexpr (GRAD) {
-                const U qr3 = s.w * ri * ri * ri;
+                const U qr3 = s.w * ri * gf;
                 gpart[0] += qr3 * dx;
                 gpart[1] += qr3 * dy;
                 gpart[2] += qr3 * dz;
@@ -1801,9 +1808,14 @@ static void run_p2p_rc(const P2PArgs<T>& args, int nwork, int n_rhs, bool far64,
                        PhaseScope& ps) {
   if constexpr (MODE == MODE_LEAF) {
     if (args.grad) {
-      // potential and gradient (Laplace kernel): one right-hand side per block
-      if (far64) run_p2p<T, double, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
-      else run_p2p<T, T, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
+      // potential and gradient: one right-hand side per block
+      if (args.kappa != 0.0) {
+        if (far64) run_p2p<T, double, MODE, 1, TCH, true, true>(args, nwork, n_rhs, s, ps);
+        else run_p2p<T, T, MODE, 1, TCH, true, true>(args, nwork, n_rhs, s, ps);
+      } else {
+        if (far64) run_p2p<T, double, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
+        else run_p2p<T, T, MODE, 1, TCH, true>(args, nwork, n_rhs, s, ps);
+      }
       return;
     }
   }

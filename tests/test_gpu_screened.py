@@ -71,11 +71,25 @@ def test_screened_batch_kernel_switch_and_errors(tmp_path):
     s1 = gpu(t1, ops, q1, "fp32")
     np.testing.assert_array_equal(gpu(t1, lap, q1, "fp32"), a)
     assert rel(s1, a) > 1e-2
-    # another root box, a gradient, the cache: refused
+    # another root box, the cache: refused
     other = K.Tree(x1 * 0.5, uniform_depth=3, center=(0.25, 0.25, 0.25), halfwidth=0.25)
     with pytest.raises(K.KifmmError, match="root half-width"):
         gpu(other, ops, q1, "fp32")
     with pytest.raises(K.KifmmError, match="Laplace"):
-        K.evaluate_gradient(t1, ops, torch.as_tensor(q1, dtype=torch.float64, device=DEV))
-    with pytest.raises(K.KifmmError, match="Laplace"):
         ops.save(str(tmp_path / "s.bin"))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "f16x3"])
+def test_screened_gradient_vs_oracle(precision):
+    x, q, p, kappa, kw = CASES["sphere8k_nc32_p5_k10"]()
+    tree = K.Tree(x, **kw)
+    ops = K.Operators.screened(p, kappa, tree)
+    got = K.evaluate_gradient(tree, ops, torch.as_tensor(q, dtype=torch.float64, device=DEV),
+                              precision=precision)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    pot, grad = OK.KIFMM(Octree(x, x, **kw), p, kappa=kappa).evaluate(q, gradient=True)
+    e = rel(got[:, 1:], grad)
+    print(f"screened gradient {precision}: {e:.2e}")
+    assert e < (1e-8 if precision == "fp64" else 2e-5)
+    assert rel(got[:, 0], pot) < TOL[precision]
