@@ -10,7 +10,7 @@ M2L as three split-BF16 products, FP64 check-to-equivalent solves and FP64
 per-target sums); the plain FP64 path runs on the same tree as the
 comparison leg, and its result is the reference of the reported error.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the evaluation runs on one GPU.
 """
 from __future__ import annotations
 
@@ -162,8 +162,8 @@ def main():
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build evaluates on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU partition is described in DESIGN.md, not built)", file=sys.stderr)
+        print(f"bench.py: the evaluation runs on one GPU; --gpus {args.gpus} is not supported "
+              "(a multi-GPU partition is designed, not implemented)", file=sys.stderr)
         return 2
 
     import torch

@@ -38,7 +38,7 @@ typedef enum {
   KIFMM_EINVAL = 1,       /* bad argument: null pointer, size, non-finite, range */
   KIFMM_ENOMEM = 2,       /* host or device allocation failed */
   KIFMM_EDEVICE = 3,      /* a HIP runtime call failed (message has its text) */
-  KIFMM_EUNSUPPORTED = 4  /* valid request this build does not implement */
+  KIFMM_EUNSUPPORTED = 4  /* valid request the library does not implement */
 } kifmm_status;
 
 /* Arithmetic of an evaluation.  In every mode the check-to-equivalent solves

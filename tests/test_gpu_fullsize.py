@@ -108,3 +108,37 @@ def test_batch_64_fullsize():
     print(f"batch of 64 fp32: rel L2 vs FP64 GPU {e64:.3e}, vs direct (4 targets per problem) {ed:.3e}")
     assert e64 <= 1e-5
     assert ed <= 1e-5
+
+
+def test_screened_1m_fullsize():
+    """The screened kernel (kappa 10) on the 1M cube, BF16x3: against its
+    FP64 path and the screened direct sum on a sample."""
+    prob = I.uniform_1m()
+    tree = tree_of(prob)
+    ops = K.Operators.screened(prob.p, 10.0, tree)
+    q = torch.as_tensor(prob.charges, dtype=torch.float64, device=DEV)
+    got = K.evaluate(tree, ops, q, precision="bf16x3")
+    ref = K.evaluate(tree, ops, q, precision="fp64")
+    torch.cuda.synchronize()
+    got, ref = got.cpu().numpy(), ref.cpu().numpy()
+    idx = I.sample_indices(prob.n, 60)
+    exact = direct.direct(prob.points, prob.charges, prob.points[idx], chunk=8, kappa=10.0)
+    e64, ed = rel(got, ref), rel(got[:, idx], exact)
+    print(f"screened 1M bf16x3: rel L2 vs FP64 GPU {e64:.3e}, vs direct (60 targets) {ed:.3e}")
+    assert e64 <= 1e-5
+    assert ed <= 1e-5
+
+
+def test_gradient_sphere_1m_fullsize():
+    """Potential + gradient on the paper-shaped sphere (points on a surface,
+    where FP32 gradient terms cancel): F16x3 against the FP64 GPU gradient."""
+    prob = I.paper_sphere_1m()
+    tree = tree_of(prob)
+    ops = K.Operators(prob.p)
+    q = torch.as_tensor(prob.charges, dtype=torch.float64, device=DEV)
+    got = K.evaluate_gradient(tree, ops, q, precision="f16x3")
+    ref = K.evaluate_gradient(tree, ops, q, precision="fp64")
+    torch.cuda.synchronize()
+    e = rel(got.cpu().numpy()[0, 1:], ref.cpu().numpy()[0, 1:])
+    print(f"sphere 1M gradient f16x3: rel L2 vs FP64 GPU {e:.3e}")
+    assert e <= 1e-5

@@ -181,3 +181,24 @@ def test_update_adaptive_equals_host_build(max_depth, ncrit):
     assert fresh.info().n_boxes == inf.n_boxes
     assert_same_tree(tree, fresh)
     np.testing.assert_array_equal(evaluate(tree, q, p), evaluate(fresh, q, p))
+
+
+def test_repeated_updates_then_host_export():
+    """Several updates in a row on an evaluated tree (the forest takes each in
+    place), then the host copy (exports, a plan rebuild) reflects the last."""
+    n, depth, p = 30000, 4, 4
+    x0, q = I.uniform_cube(n, seed=130)
+    tree = K.Tree(x0, uniform_depth=depth, **CUBE)
+    evaluate(tree, q, p)
+    xs = [same_leaves(x0, depth, seed=131 + k) for k in range(3)]
+    for x in xs:
+        tree.update_points(dev(x))
+        got = evaluate(tree, q, p)
+    fresh = K.Tree(xs[-1], uniform_depth=depth, **CUBE)
+    np.testing.assert_array_equal(got, evaluate(fresh, q, p))
+    assert_same_tree(tree, fresh)
+    K.set_tuning("m2l_tile_cols", 128)  # new plans: built from the refreshed host copy
+    try:
+        np.testing.assert_array_equal(evaluate(tree, q, p), evaluate(fresh, q, p))
+    finally:
+        K.set_tuning("m2l_tile_cols", 64)

@@ -30,7 +30,7 @@ def _uniform_pair_counts(depth):
 
 
 def test_uniform_counts_closed_form():
-    # the survey-time grid counts: depth 3 -> 10,648 U and 56,448 V pairs
+    # exact grid counts: depth 3 -> 10,648 U and 56,448 V pairs
     assert _uniform_pair_counts(3) == (10648, 56448)
     assert _uniform_pair_counts(5) == (830584, 6039504)
     x, _ = I.uniform_cube(20000, seed=0)
