@@ -235,3 +235,21 @@ def test_operator_cache_roundtrip_and_rejections(tmp_path):
     b = K.Operators.cached(3, cache_dir=str(tmp_path))
     np.testing.assert_array_equal(a.export(1), b.export(1))
     assert K.lib().kifmm_precompute_operators_ex(4, 1e-9, 2, None) == 1  # EINVAL
+
+
+def test_screened_operators_and_update_arguments_on_host():
+    """Host-side argument checks of the screened-kernel precompute and the
+    point update (no device work is reached)."""
+    import ctypes as C
+    L = K.lib()
+    h = C.c_void_p()
+    assert L.kifmm_precompute_operators_screened(4, 1e-9, 0.0, 0.5, 4, 0, C.byref(h)) == 1   # kappa
+    assert L.kifmm_precompute_operators_screened(4, 1e-9, 2.0, 0.0, 4, 0, C.byref(h)) == 1   # root
+    assert L.kifmm_precompute_operators_screened(4, 1e-9, 2.0, 0.5, 1, 0, C.byref(h)) == 1   # max_level
+    assert L.kifmm_precompute_operators_screened(4, 1e-9, 2.0, 0.5, 4, 8, C.byref(h)) == 1   # flag
+    assert L.kifmm_precompute_operators_screened(4, 1e-9, 2.0, 0.5, 3, 0, C.byref(h)) == 0   # host SVD
+    L.kifmm_ops_destroy(h)
+    assert L.kifmm_tree_update_points(None, None, None, None) == 1
+    x = np.random.default_rng(0).random((100, 3))
+    t = K.Tree(x, uniform_depth=2, center=(0.5, 0.5, 0.5), halfwidth=0.5)
+    assert L.kifmm_tree_update_points(t.handle, None, None, None) == 1
