@@ -20,10 +20,10 @@ struct kifmm_tree {
   std::unique_ptr<kifmm::HostTree> host;
   std::unique_ptr<kifmm::EvalState> state;  // single-tree forest + device state
   int state_n = 0;  // operator size the cached forest was built for
-  // points re-sorted on the device and not yet copied into `host`
-  kifmm::PendingPoints* pending = nullptr;
+  // device state of the point re-sort (the host copy may lag its last order)
+  kifmm::PendingPoints* sort = nullptr;
   ~kifmm_tree() {
-    if (pending) kifmm::pending_free(pending);
+    if (sort) kifmm::pending_free(sort);
   }
 };
 
@@ -120,11 +120,7 @@ static kifmm_status guard(F&& f) {
 // The host copy of a tree, refreshed first from a device point update.
 static const HostTree& host_of(const kifmm_tree* tree) {
   auto* t = const_cast<kifmm_tree*>(tree);
-  if (t->pending) {
-    pending_to_host(t->pending, *t->host);
-    pending_free(t->pending);
-    t->pending = nullptr;
-  }
+  if (pending_stale(t->sort)) pending_to_host(*t->sort, *t->host);
   return *t->host;
 }
 
@@ -220,12 +216,19 @@ kifmm_status kifmm_tree_update_points(kifmm_tree* tree, const double* src_xyz, c
                                       void* hip_stream) {
   return guard([&] {
     if (!tree) raise(KIFMM_EINVAL, "tree_update_points: null tree");
+    if (!src_xyz) raise(KIFMM_EINVAL, "tree_update_points: null source coordinates");
+    if (tree->sort && pending_device(tree->sort) != current_device()) {
+      // the sort state lives on another device: bring the host copy up to
+      // date, then start over on this one
+      host_of(tree);
+      pending_free(tree->sort);
+      tree->sort = nullptr;
+    }
+    if (!tree->sort) tree->sort = sort_state_create(*tree->host);
     EvalState* st = tree->state.get();
-    PendingPoints* p = update_points_device(*tree->host, st, src_xyz, tgt_xyz, hip_stream);
+    update_points_device(*tree->sort, *tree->host, st, src_xyz, tgt_xyz, hip_stream);
     purge_batches(tree, nullptr);
     if (tgt_xyz && tgt_xyz != src_xyz) tree->host->tgt_is_src = false;
-    if (tree->pending) pending_free(tree->pending);
-    tree->pending = p;
     // no forest on this device took the new order in place: refresh the
     // host copy now, and build the evaluation state from it when needed
     if (!st || dev_point_view(*st).device != current_device()) {
@@ -324,7 +327,7 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
     check_kernel(*t->host, *ops->host);
     bool rebuild =
         !t->state || t->state_n != n || !plan_current(*t->state->host, TB, TBm, n, n_rhs, per_level);
-    if (t->pending && (rebuild || dev_point_view(*t->state).device != current_device())) {
+    if (pending_stale(t->sort) && (rebuild || dev_point_view(*t->state).device != current_device())) {
       // the device-updated points live only in the resident forest: a new
       // forest (new plans, or another device) is built from the host copy
       host_of(t);

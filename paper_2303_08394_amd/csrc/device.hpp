@@ -70,19 +70,23 @@ struct DevPointView {
 };
 DevPointView dev_point_view(const EvalState& st);
 
-// New point positions of a tree, sorted on the device (see
-// tree_update.hip) and held there until the host copy of the tree is
-// refreshed from them.
+// Device state of the point re-sort of one tree (see tree_update.hip): the
+// tree's boxes and leaf occupancy on the device, sort scratch, and the last
+// accepted sorted order, kept between updates.
 struct PendingPoints;
-// Sorts src (and tgt; null: the sources) into T's leaves on the device and,
-// if st has a forest resident on the current device, rewrites it in place.
+PendingPoints* sort_state_create(const HostTree& T);
+// Sorts src (and tgt; null: the sources) into T's leaves on the current
+// device and, if st has a forest resident there, rewrites it in place.
 // Throws Error EINVAL if a point falls outside the leaves of its kind that
-// were occupied, or one of those empties (T and st unchanged).  Synchronises
-// the stream.
-PendingPoints* update_points_device(const HostTree& T, EvalState* st, const double* src, const double* tgt,
-                                    void* stream);
-// Copies the sorted order, coordinates, keys and box ranges into T.
-void pending_to_host(PendingPoints* p, HostTree& T);
+// were occupied, or one of those empties (T, st and the last accepted order
+// unchanged).  Synchronises the stream.
+void update_points_device(PendingPoints& P, const HostTree& T, EvalState* st, const double* src,
+                          const double* tgt, void* stream);
+// Copies the last accepted order, coordinates, keys and box ranges into T
+// (if it lags them).
+void pending_to_host(PendingPoints& P, HostTree& T);
+bool pending_stale(const PendingPoints* p);
+int pending_device(const PendingPoints* p);
 void pending_free(PendingPoints* p);
 
 // smallest order at which FP32-bulk modes evaluate L2P/M2P terms in FP64

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -224,10 +225,11 @@ __device__ inline int64_t lower_bound_u64(const u64* a, int64_t n, u64 v) {
   return lo;
 }
 
-// New point range of every box; flags a leaf whose emptiness changed and
-// counts the points that fall in leaves.
+// New point range of every box; flags a leaf whose emptiness changed (occ:
+// 1 for the leaves that held points of this kind) and counts the points that
+// fall in leaves.
 __global__ void ranges_kernel(const int32_t* __restrict__ anchor, const int32_t* __restrict__ level,
-                              const int32_t* __restrict__ is_leaf, const int64_t* __restrict__ old_rng,
+                              const int32_t* __restrict__ is_leaf, const uint8_t* __restrict__ occ,
                               int32_t nbox, int L, const u64* __restrict__ skeys, int64_t n,
                               int2* __restrict__ out, unsigned* __restrict__ flag,
                               unsigned long long* __restrict__ in_leaves) {
@@ -240,8 +242,7 @@ __global__ void ranges_kernel(const int32_t* __restrict__ anchor, const int32_t*
   const int64_t e = lower_bound_u64(skeys, n, (m + 1) << sh);
   out[g] = make_int2(int(b), int(e));
   if (is_leaf[g]) {
-    const bool was = old_rng[2 * g + 1] > old_rng[2 * g];
-    if ((e > b) != was) atomicOr(flag, 1u);
+    if ((e > b) != (occ[g] != 0)) atomicOr(flag, 1u);
     atomicAdd(in_leaves, (unsigned long long)(e - b));
   }
 }
@@ -256,107 +257,142 @@ T* dalloc(std::vector<void*>& owned, size_t count) {
 
 }  // namespace
 
-// One sorted point set, resident on the device until copied to the host.
+// One sorted point set.
 struct SortedSet {
-  int64_t n = 0;
   u64* keys = nullptr;         // [n] sorted leaf keys
   int32_t* perm = nullptr;     // [n] sorted position -> caller index
   double* xyz = nullptr;       // [n][3] sorted coordinates
   double4* rel = nullptr;      // [n] leaf-frame coordinates
   int2* ranges = nullptr;      // [nbox]
-  std::vector<void*> owned;
 };
 
+// Per-tree device state of the re-sort, kept between updates: the tree's box
+// table and leaf occupancy (uploaded once), sort scratch, and two output sets
+// per kind, so that a rejected update leaves the last accepted one intact.
 struct PendingPoints {
   int device = -1;
   int32_t nbox = 0;
-  SortedSet src, tgt;
-  bool tgt_is_src = false;
+  int64_t nsrc = 0, ntgt = 0;
+  int nleaves = 0, nblk = 0, nchunk = 0;
+  int32_t *anchor = nullptr, *level = nullptr, *leaf = nullptr, *leaves = nullptr;
+  uint8_t *occ_src = nullptr, *occ_tgt = nullptr;
+  u64* k0 = nullptr;
+  int32_t* v0 = nullptr;
+  uint32_t *hist = nullptr, *totals = nullptr;
+  unsigned long long* stat = nullptr;  // [4]: flag, source count, target count
+  SortedSet src[2], tgt[2];
+  int cur = -1;             // output set of the last accepted update
+  bool stale_host = false;  // the host copy of the tree lags set `cur`
+  bool tgt_sep = false;     // set `cur` has its own targets
+  std::vector<void*> allocs;
   ~PendingPoints() {
-    for (void* p : src.owned) (void)hipFree(p);
-    for (void* p : tgt.owned) (void)hipFree(p);
+    for (void* p : allocs) (void)hipFree(p);
   }
 };
 
-struct FreeAll {
-  std::vector<void*> v;
-  ~FreeAll() {
-    for (void* p : v) (void)hipFree(p);
-  }
-};
+static void alloc_set(PendingPoints& P, SortedSet& S, int64_t n) {
+  S.keys = dalloc<u64>(P.allocs, n);
+  S.perm = dalloc<int32_t>(P.allocs, n);
+  S.xyz = dalloc<double>(P.allocs, size_t(n) * 3);
+  S.rel = dalloc<double4>(P.allocs, n);
+  S.ranges = dalloc<int2>(P.allocs, P.nbox);
+}
 
-static void sort_set(const HostTree& T, const double* xyz, int64_t n, const std::vector<int64_t>& old_rng,
-                     const int32_t* d_anchor, const int32_t* d_level, const int32_t* d_leaf,
-                     const int32_t* d_leaves, int nleaves, hipStream_t s, SortedSet& S, unsigned* d_flag,
-                     unsigned long long* d_count) {
+PendingPoints* sort_state_create(const HostTree& T) {
+  auto P = std::make_unique<PendingPoints>();
+  P->device = current_device();
+  P->nbox = T.nbox;
+  P->nsrc = T.nsrc;
+  P->ntgt = T.ntgt;
+  const int64_t nmax = std::max(T.nsrc, T.ntgt);
+  P->nblk = int((nmax + kTile - 1) / kTile);
+  const int64_t m = int64_t(kThreads) * P->nblk;
+  P->nchunk = int((m + 1023) / 1024);
+  if (P->nchunk > 1024 * 64) raise(KIFMM_EUNSUPPORTED, "update_points: too many points for one sort");
+  std::vector<int32_t> isleaf(T.leaf.begin(), T.leaf.end()), leaves;
+  std::vector<uint8_t> os(T.nbox, 0), ot(T.nbox, 0);
+  for (int32_t g = 0; g < T.nbox; ++g) {
+    if (T.leaf[g]) leaves.push_back(g);
+    os[g] = T.send[g] > T.sbeg[g] ? 1 : 0;
+    ot[g] = T.tend[g] > T.tbeg[g] ? 1 : 0;
+  }
+  P->nleaves = int(leaves.size());
+  P->anchor = dalloc<int32_t>(P->allocs, T.anchor.size());
+  P->level = dalloc<int32_t>(P->allocs, T.level.size());
+  P->leaf = dalloc<int32_t>(P->allocs, isleaf.size());
+  P->leaves = dalloc<int32_t>(P->allocs, leaves.size());
+  P->occ_src = dalloc<uint8_t>(P->allocs, os.size());
+  P->occ_tgt = dalloc<uint8_t>(P->allocs, ot.size());
+  HIPCHECK(hipMemcpy(P->anchor, T.anchor.data(), T.anchor.size() * 4, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(P->level, T.level.data(), T.level.size() * 4, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(P->leaf, isleaf.data(), isleaf.size() * 4, hipMemcpyHostToDevice));
+  if (!leaves.empty()) HIPCHECK(hipMemcpy(P->leaves, leaves.data(), leaves.size() * 4, hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(P->occ_src, os.data(), os.size(), hipMemcpyHostToDevice));
+  HIPCHECK(hipMemcpy(P->occ_tgt, ot.data(), ot.size(), hipMemcpyHostToDevice));
+  P->k0 = dalloc<u64>(P->allocs, nmax);
+  P->v0 = dalloc<int32_t>(P->allocs, nmax);
+  P->hist = dalloc<uint32_t>(P->allocs, size_t(m));
+  P->totals = dalloc<uint32_t>(P->allocs, P->nchunk);
+  P->stat = dalloc<unsigned long long>(P->allocs, 4);
+  for (int k = 0; k < 2; ++k) alloc_set(*P, P->src[k], T.nsrc);
+  return P.release();
+}
+
+static void sort_set(PendingPoints& P, const HostTree& T, const double* xyz, int64_t n, const uint8_t* occ,
+                     hipStream_t s, SortedSet& S, unsigned long long* d_count) {
   Frame f;
   for (int d = 0; d < 3; ++d) f.lo[d] = T.lo[d];
   f.r0 = T.r0;
   f.L = T.key_level;
-  S.n = n;
-  FreeAll tmp;
-  u64* k0 = dalloc<u64>(tmp.v, n);
-  int32_t* v0 = dalloc<int32_t>(tmp.v, n);
-  u64* k1 = dalloc<u64>(S.owned, n);
-  int32_t* v1 = dalloc<int32_t>(S.owned, n);
   const unsigned grid = unsigned((n + 255) / 256);
-  hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, k0, v0);
+  hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, P.k0, P.v0);
   LAUNCHCHECK("key_kernel");
   const int nblk = int((n + kTile - 1) / kTile);
-  uint32_t* hist = dalloc<uint32_t>(tmp.v, size_t(kThreads) * nblk);
   const int64_t m = int64_t(kThreads) * nblk;  // scanned entries
   const int nchunk = int((m + 1023) / 1024);
-  if (nchunk > 1024 * 64) raise(KIFMM_EUNSUPPORTED, "update_points: too many points for one sort");
-  uint32_t* totals = dalloc<uint32_t>(tmp.v, nchunk);
   const int passes = (3 * T.key_level + 7) / 8;
-  u64 *kin = k0, *kout = k1;
-  int32_t *vin = v0, *vout = v1;
+  u64 *kin = P.k0, *kout = S.keys;
+  int32_t *vin = P.v0, *vout = S.perm;
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, n, 8 * p, hist, nblk);
+    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, n, 8 * p, P.hist, nblk);
     LAUNCHCHECK("radix_hist_kernel");
-    hipLaunchKernelGGL(scan_chunks_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, hist, m, totals);
+    hipLaunchKernelGGL(scan_chunks_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, P.hist, m, P.totals);
     LAUNCHCHECK("scan_chunks_kernel");
-    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(1024), 0, s, totals, nchunk);
+    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(1024), 0, s, P.totals, nchunk);
     LAUNCHCHECK("scan_totals_kernel");
-    hipLaunchKernelGGL(scan_add_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, hist, m, totals);
+    hipLaunchKernelGGL(scan_add_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, P.hist, m, P.totals);
     LAUNCHCHECK("scan_add_kernel");
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, vin, n, 8 * p, hist, nblk,
-                       kout, vout);
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, vin, n, 8 * p, P.hist,
+                       nblk, kout, vout);
     LAUNCHCHECK("radix_scatter_kernel");
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  // the sorted keys and order are in (kin, vin): keep those buffers
-  if (kin == k0) {
-    HIPCHECK(hipMemcpyAsync(k1, k0, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
-    HIPCHECK(hipMemcpyAsync(v1, v0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
+  // the sorted keys and order are in (kin, vin); the set keeps its own
+  if (kin == P.k0) {
+    HIPCHECK(hipMemcpyAsync(S.keys, P.k0, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(S.perm, P.v0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   }
-  S.keys = k1;
-  S.perm = v1;
-  S.xyz = dalloc<double>(S.owned, size_t(n) * 3);
-  S.rel = dalloc<double4>(S.owned, n);
   hipLaunchKernelGGL(gather_sorted_kernel, dim3(grid), dim3(256), 0, s, xyz, S.perm, n, S.xyz);
   LAUNCHCHECK("gather_sorted_kernel");
-  int64_t* d_old = dalloc<int64_t>(tmp.v, old_rng.size());
-  HIPCHECK(hipMemcpyAsync(d_old, old_rng.data(), old_rng.size() * 8, hipMemcpyHostToDevice, s));
-  S.ranges = dalloc<int2>(S.owned, T.nbox);
-  hipLaunchKernelGGL(ranges_kernel, dim3(unsigned((T.nbox + 255) / 256)), dim3(256), 0, s, d_anchor, d_level,
-                     d_leaf, d_old, T.nbox, T.key_level, S.keys, n, S.ranges, d_flag, d_count);
+  hipLaunchKernelGGL(ranges_kernel, dim3(unsigned((T.nbox + 255) / 256)), dim3(256), 0, s, P.anchor, P.level,
+                     P.leaf, occ, T.nbox, T.key_level, S.keys, n, S.ranges,
+                     reinterpret_cast<unsigned*>(P.stat), d_count);
   LAUNCHCHECK("ranges_kernel");
-  if (nleaves > 0) {
-    hipLaunchKernelGGL(leaf_frame_kernel, dim3(unsigned(nleaves)), dim3(64), 0, s, d_leaves, d_anchor, d_level,
-                       S.ranges, f, S.xyz, S.rel);
+  if (P.nleaves > 0) {
+    hipLaunchKernelGGL(leaf_frame_kernel, dim3(unsigned(P.nleaves)), dim3(64), 0, s, P.leaves, P.anchor,
+                       P.level, S.ranges, f, S.xyz, S.rel);
     LAUNCHCHECK("leaf_frame_kernel");
   }
-  // the host copy of old_rng and the scratch must outlive the work above
-  HIPCHECK(hipStreamSynchronize(s));
 }
 
-PendingPoints* update_points_device(const HostTree& T, EvalState* st, const double* src, const double* tgt,
-                                    void* stream) {
+void update_points_device(PendingPoints& P, const HostTree& T, EvalState* st, const double* src,
+                          const double* tgt, void* stream) {
   if (!src) raise(KIFMM_EINVAL, "update_points: null source coordinates");
   if (!tgt && !T.tgt_is_src)
     raise(KIFMM_EINVAL, "update_points: the tree has separate targets; pass their coordinates");
+  if (P.device != current_device() || P.nbox != T.nbox || P.nsrc != T.nsrc || P.ntgt != T.ntgt)
+    raise(KIFMM_EINVAL, "update_points: sort state of another device or tree");
   for (const double* p : {src, tgt}) {
     if (!p) continue;
     hipPointerAttribute_t at;
@@ -366,72 +402,45 @@ PendingPoints* update_points_device(const HostTree& T, EvalState* st, const doub
     }
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  auto P = std::make_unique<PendingPoints>();
-  P->device = current_device();
-  P->nbox = T.nbox;
-  P->tgt_is_src = tgt == nullptr;
-  FreeAll tmp;
-  std::vector<int32_t> isleaf(T.leaf.begin(), T.leaf.end());
-  std::vector<int32_t> leaves;
-  for (int32_t g = 0; g < T.nbox; ++g)
-    if (T.leaf[g]) leaves.push_back(g);
-  int32_t* d_anchor = dalloc<int32_t>(tmp.v, T.anchor.size());
-  int32_t* d_level = dalloc<int32_t>(tmp.v, T.level.size());
-  int32_t* d_leaf = dalloc<int32_t>(tmp.v, isleaf.size());
-  int32_t* d_leaves = dalloc<int32_t>(tmp.v, leaves.size());
-  unsigned long long* d_stat = dalloc<unsigned long long>(tmp.v, 4);  // flag (as unsigned), count per set
-  HIPCHECK(hipMemcpyAsync(d_anchor, T.anchor.data(), T.anchor.size() * 4, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(d_level, T.level.data(), T.level.size() * 4, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(d_leaf, isleaf.data(), isleaf.size() * 4, hipMemcpyHostToDevice, s));
-  if (!leaves.empty())
-    HIPCHECK(hipMemcpyAsync(d_leaves, leaves.data(), leaves.size() * 4, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemsetAsync(d_stat, 0, 4 * sizeof(unsigned long long), s));
-  unsigned* d_flag = reinterpret_cast<unsigned*>(d_stat);
-  std::vector<int64_t> old(2 * size_t(T.nbox));
-  for (int32_t g = 0; g < T.nbox; ++g) {
-    old[2 * g] = T.sbeg[g];
-    old[2 * g + 1] = T.send[g];
-  }
-  sort_set(T, src, T.nsrc, old, d_anchor, d_level, d_leaf, d_leaves, int(leaves.size()), s, P->src, d_flag,
-           d_stat + 1);
-  if (tgt) {
-    for (int32_t g = 0; g < T.nbox; ++g) {
-      old[2 * g] = T.tbeg[g];
-      old[2 * g + 1] = T.tend[g];
-    }
-    sort_set(T, tgt, T.ntgt, old, d_anchor, d_level, d_leaf, d_leaves, int(leaves.size()), s, P->tgt, d_flag,
-             d_stat + 2);
-  }
+  const int nxt = P.cur == 0 ? 1 : 0;  // the set not holding the last accepted update
+  if (tgt && !P.tgt[nxt].keys) alloc_set(P, P.tgt[nxt], T.ntgt);
+  HIPCHECK(hipMemsetAsync(P.stat, 0, 4 * sizeof(unsigned long long), s));
+  sort_set(P, T, src, T.nsrc, P.occ_src, s, P.src[nxt], P.stat + 1);
+  if (tgt) sort_set(P, T, tgt, T.ntgt, P.occ_tgt, s, P.tgt[nxt], P.stat + 2);
   unsigned long long stat[4];
-  HIPCHECK(hipMemcpyAsync(stat, d_stat, sizeof(stat), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(stat, P.stat, sizeof(stat), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
   if ((stat[0] & 0xffffffffull) != 0 || int64_t(stat[1]) != T.nsrc || (tgt && int64_t(stat[2]) != T.ntgt))
     raise(KIFMM_EINVAL,
           "update_points: the points occupy other leaves than the tree's (rebuild the tree on the host)");
   // the evaluation state resident on this device takes the new order in place
+  const SortedSet& ss = P.src[nxt];
+  const SortedSet& ts = tgt ? P.tgt[nxt] : ss;
   DevPointView v = st ? dev_point_view(*st) : DevPointView{};
-  if (v.device == P->device && v.nbox == T.nbox) {
-    const SortedSet& ts = tgt ? P->tgt : P->src;
-    HIPCHECK(hipMemcpyAsync(v.box_src, P->src.ranges, size_t(T.nbox) * 8, hipMemcpyDeviceToDevice, s));
-    HIPCHECK(hipMemcpyAsync(v.src64, P->src.rel, size_t(T.nsrc) * 32, hipMemcpyDeviceToDevice, s));
-    HIPCHECK(hipMemcpyAsync(v.src_perm, P->src.perm, size_t(T.nsrc) * 4, hipMemcpyDeviceToDevice, s));
+  if (v.device == P.device && v.nbox == T.nbox) {
+    HIPCHECK(hipMemcpyAsync(v.box_src, ss.ranges, size_t(T.nbox) * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(v.src64, ss.rel, size_t(T.nsrc) * 32, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemcpyAsync(v.src_perm, ss.perm, size_t(T.nsrc) * 4, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemcpyAsync(v.box_tgt, ts.ranges, size_t(T.nbox) * 8, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemcpyAsync(v.tgt64, ts.rel, size_t(T.ntgt) * 32, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemcpyAsync(v.tgt_perm, ts.perm, size_t(T.ntgt) * 4, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
   }
-  return P.release();
+  P.cur = nxt;
+  P.tgt_sep = tgt != nullptr;
+  P.stale_host = true;
 }
 
-static void set_to_host(const SortedSet& S, int32_t nbox, std::vector<int64_t>& perm, std::vector<double>& xyz,
-                        std::vector<uint64_t>& keys, std::vector<int64_t>& beg, std::vector<int64_t>& end) {
-  std::vector<u64> k(S.n);
-  std::vector<int32_t> p(S.n);
+static void set_to_host(const SortedSet& S, int64_t n, int32_t nbox, std::vector<int64_t>& perm,
+                        std::vector<double>& xyz, std::vector<uint64_t>& keys, std::vector<int64_t>& beg,
+                        std::vector<int64_t>& end) {
+  std::vector<u64> k(n);
+  std::vector<int32_t> p(n);
   std::vector<int2> r(nbox);
-  xyz.resize(3 * size_t(S.n));
-  HIPCHECK(hipMemcpy(k.data(), S.keys, size_t(S.n) * 8, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(p.data(), S.perm, size_t(S.n) * 4, hipMemcpyDeviceToHost));
-  HIPCHECK(hipMemcpy(xyz.data(), S.xyz, size_t(S.n) * 24, hipMemcpyDeviceToHost));
+  xyz.resize(3 * size_t(n));
+  HIPCHECK(hipMemcpy(k.data(), S.keys, size_t(n) * 8, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(p.data(), S.perm, size_t(n) * 4, hipMemcpyDeviceToHost));
+  HIPCHECK(hipMemcpy(xyz.data(), S.xyz, size_t(n) * 24, hipMemcpyDeviceToHost));
   HIPCHECK(hipMemcpy(r.data(), S.ranges, size_t(nbox) * 8, hipMemcpyDeviceToHost));
   keys.assign(k.begin(), k.end());
   perm.assign(p.begin(), p.end());
@@ -441,16 +450,21 @@ static void set_to_host(const SortedSet& S, int32_t nbox, std::vector<int64_t>& 
   }
 }
 
-void pending_to_host(PendingPoints* P, HostTree& T) {
+void pending_to_host(PendingPoints& P, HostTree& T) {
+  if (!P.stale_host) return;
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
-  if (dev != P->device) HIPCHECK(hipSetDevice(P->device));
-  set_to_host(P->src, P->nbox, T.sperm, T.sxyz, T.skey, T.sbeg, T.send);
-  const SortedSet& ts = P->tgt_is_src ? P->src : P->tgt;
-  set_to_host(ts, P->nbox, T.tperm, T.txyz, T.tkey, T.tbeg, T.tend);
-  if (dev != P->device) HIPCHECK(hipSetDevice(dev));
+  if (dev != P.device) HIPCHECK(hipSetDevice(P.device));
+  const SortedSet& ss = P.src[P.cur];
+  set_to_host(ss, P.nsrc, P.nbox, T.sperm, T.sxyz, T.skey, T.sbeg, T.send);
+  const SortedSet& ts = P.tgt_sep ? P.tgt[P.cur] : ss;
+  set_to_host(ts, P.ntgt, P.nbox, T.tperm, T.txyz, T.tkey, T.tbeg, T.tend);
+  if (dev != P.device) HIPCHECK(hipSetDevice(dev));
+  P.stale_host = false;
 }
 
+bool pending_stale(const PendingPoints* P) { return P && P->stale_host; }
+int pending_device(const PendingPoints* P) { return P ? P->device : -1; }
 void pending_free(PendingPoints* P) { delete P; }
 
 }  // namespace kifmm
