@@ -323,3 +323,19 @@ def test_batch_mixed_m2l_schemes_equal_individual_runs():
             np.testing.assert_array_equal(m[r], gpu_eval(trees[0], 5, qm[r], "fp32")[0])
     finally:
         K.set_tuning("m2l_pair_fill", 40)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp32"])
+def test_zero_and_scaled_charges(precision):
+    """Zero charges give zero potentials; scaling the charges by 2^-66 or 2^66
+    (about 1e-20 and 1e20) scales the potentials exactly: every rounding of
+    the path commutes with a power of two while nothing leaves the normal
+    range (the FP16 split rescales the densities by a power of two taken from
+    their largest magnitude, the BF16 split shares FP32's exponent range)."""
+    x, q = I.uniform_cube(5000, seed=50, charge_range=(-1, 1))
+    tree = K.Tree(x, uniform_depth=3, **CUBE)
+    assert np.all(gpu_eval(tree, 5, 0 * q, precision) == 0)
+    base = gpu_eval(tree, 5, q, precision)
+    for s in (2.0 ** -66, 2.0 ** 66):
+        got = gpu_eval(tree, 5, s * q, precision)
+        np.testing.assert_array_equal(got / s, base)
