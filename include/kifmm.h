@@ -204,6 +204,10 @@ kifmm_status kifmm_ops_load(const char* path, int32_t p, double rcond, kifmm_ops
 kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out,
                               int64_t n_out);
 int32_t kifmm_ops_n(const kifmm_ops* ops); /* surface points n, or -1 */
+/* Table sets of `ops`: 1 (Laplace kernel), or max_level + 1 (screened kernel:
+ * kifmm_ops_export then returns every table as [levels][...], set l for
+ * boxes of half-width root_halfwidth / 2^l, sets 0 and 1 zero); -1 for NULL. */
+int32_t kifmm_ops_levels(const kifmm_ops* ops);
 
 /* Evaluate the potentials (one hipGraph replay on a non-default stream, see
  * the "graph" tuning key).  charges: DEVICE [n_rhs][n_src] (caller order),

@@ -289,6 +289,8 @@ kifmm_status kifmm_ops_load(const char* path, int32_t p, double rcond, kifmm_ops
 
 int32_t kifmm_ops_n(const kifmm_ops* ops) { return ops ? ops->host->n : -1; }
 
+int32_t kifmm_ops_levels(const kifmm_ops* ops) { return ops ? ops->host->levels : -1; }
+
 kifmm_status kifmm_ops_export(const kifmm_ops* ops, int32_t which, double* out, int64_t n_out) {
   if (!ops || !out) return fail(KIFMM_EINVAL, "ops_export: null argument");
   const HostOps& H = *ops->host;

@@ -46,7 +46,7 @@ EXPORTED = [
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
     "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_precompute_operators_screened",
     "kifmm_ops_save", "kifmm_ops_load",
-    "kifmm_ops_export", "kifmm_ops_n", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
+    "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
@@ -77,6 +77,8 @@ def lib():
     L.kifmm_ops_export.argtypes = [P, I32, D, I64]
     L.kifmm_ops_n.argtypes = [P]
     L.kifmm_ops_n.restype = I32
+    L.kifmm_ops_levels.argtypes = [P]
+    L.kifmm_ops_levels.restype = I32
     L.kifmm_evaluate.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
     L.kifmm_evaluate_gradient.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
     L.kifmm_evaluate_batch.argtypes = [I32, C.POINTER(P), P, C.POINTER(P), C.POINTER(P), I32,
@@ -250,10 +252,14 @@ class Operators:
         return self._h
 
     def export(self, which: int) -> np.ndarray:
+        """A table (kifmm_ops_export); screened-kernel tables 1..5 come as
+        [levels][...] (set l for boxes of half-width r0 / 2^l)."""
         n = self.n
         shapes = {0: (n, 3), 1: (n, n), 2: (n, n), 3: (8, n, n), 4: (8, n, n),
                   5: (316, n, n), 6: (316, 3)}
-        out = np.zeros(shapes[which])
+        lev = lib().kifmm_ops_levels(self._h)
+        shape = (lev,) + shapes[which] if lev > 1 and 1 <= which <= 5 else shapes[which]
+        out = np.zeros(shape)
         _check(lib().kifmm_ops_export(self._h, which, _dptr(out), out.size))
         return out
 

@@ -253,3 +253,28 @@ def test_screened_operators_and_update_arguments_on_host():
     x = np.random.default_rng(0).random((100, 3))
     t = K.Tree(x, uniform_depth=2, center=(0.5, 0.5, 0.5), halfwidth=0.5)
     assert L.kifmm_tree_update_points(t.handle, None, None, None) == 1
+
+
+def test_screened_tables_match_oracle_per_level():
+    """Screened-kernel tables (host precompute) against the oracle's operators,
+    which it forms at each level from the actual box size: in the tables'
+    units set l is r_l times the physical operator (the pseudo-inverses
+    1 / r_l times), r_l = r0 / 2^l."""
+    import ctypes as C
+    p, kappa, r0, lmax = 4, 3.0, 1.0, 4
+    h = C.c_void_p()
+    K._check(K.lib().kifmm_precompute_operators_screened(p, 1e-9, kappa, r0, lmax, 0, C.byref(h)))
+    ops = K.Operators(p, _handle=h)
+    assert K.lib().kifmm_ops_levels(h) == lmax + 1
+    uc2e, m2m, l2l, m2l, offs = ops.export(1), ops.export(3), ops.export(4), ops.export(5), ops.export(6)
+    assert uc2e.shape == (lmax + 1, ops.n, ops.n) and np.all(uc2e[:2] == 0)
+    tree = Octree(np.zeros((1, 3)), np.zeros((1, 3)), uniform_depth=0, center=(0, 0, 0), halfwidth=r0)
+    o = OK.KIFMM(tree, p, kappa=kappa)
+    for lev in (2, 4):
+        r = r0 / 2 ** lev
+        assert np.linalg.norm(uc2e[lev] - o.uc2e(lev) / r) / np.linalg.norm(o.uc2e(lev) / r) < 1e-9
+        for k in (0, 123, 315):
+            np.testing.assert_allclose(m2l[lev, k], r * o.m2l(lev, tuple(offs[k].astype(int))), rtol=1e-12)
+        oc = (1, 0, 1)
+        np.testing.assert_allclose(m2m[lev, 5], r * o.m2m(lev + 1, oc), rtol=1e-12)
+        np.testing.assert_allclose(l2l[lev, 5], r * o.l2l(lev, oc), rtol=1e-12)
