@@ -62,22 +62,27 @@ def _kernel_source_sha() -> str:
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def _measured_traffic(precision: str):
-    """HBM bytes per M2L launch from the committed rocprofv3 PMC summary
-    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when the summary is missing or the kernel source changed since."""
-    path = os.path.join(ROOT, "profiles", "m2l_traffic_uniform1m_p6.txt")
+def _profile_value(name: str, key: str):
+    """A value from a committed rocprofv3 PMC summary under profiles/, or None
+    when the summary is missing, lacks the key, or was taken on another
+    version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
-            kv[k.strip()] = v.strip()
+            kv[k.strip()] = v.strip().split()[0] if v.strip() else ""
     if kv.get("evaluate_hip_sha256_16") != _kernel_source_sha():
         return None
-    key = f"traffic_bytes_{precision}"
     return float(kv[key]) if key in kv else None
+
+
+def _measured_traffic(precision: str):
+    """HBM bytes per M2L launch (FETCH_SIZE + WRITE_SIZE, scaled by the
+    copy-kernel calibration)."""
+    return _profile_value("m2l_traffic_uniform1m_p6.txt", f"traffic_bytes_{precision}")
 
 
 # Headline mixed mode: FP32 bulk, FP64 solves and per-target sums, M2L as
@@ -349,6 +354,11 @@ def main():
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
     roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
+    if args.config == "uniform_1m" and dom == "m2l" and not args.m2l_tile:
+        # SQ_VALU_MFMA_BUSY_CYCLES over the launch's cycles, and the clock the
+        # GRBM counter reads meanwhile (rocprofv3, same kernel source)
+        roof["mfma_busy_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_mfma_busy_{precision}")
+        roof["clock_ghz_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_clock_ghz_{precision}")
 
     if not batch and n_rhs == 1 and not args.no_gradient and not kappa:
         # potentials + gradients (kifmm_evaluate_gradient), graph replays as
