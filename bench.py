@@ -9,6 +9,10 @@ fastest mixed-precision path within the 1e-5 bound (FP32 bulk arithmetic,
 M2L as three split-BF16 products, FP64 check-to-equivalent solves and FP64
 per-target sums); the plain FP64 path runs on the same tree as the
 comparison leg, and its result is the reference of the reported error.
+Before timing, the launch layout (M2L tile width and split, pair-scheme
+threshold, near-field schedule) is searched on the workload itself by
+paper_2303_08394_amd.autotune and the fastest left in force (--no-autotune
+keeps the library defaults); the line reports the layout that was timed.
 
 Prints one JSON line.  --gpus N with N > 1 exits: the evaluation runs on one GPU.
 """
@@ -159,6 +163,8 @@ def main():
     ap.add_argument("--no-gradient", action="store_true", help="skip the potential + gradient leg")
     ap.add_argument("--direct-sample", type=int, default=200)
     ap.add_argument("--m2l-tile", type=int, default=0, help="M2L output columns per block (64/128/192)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-layout search (paper_2303_08394_amd.autotune) before timing")
     ap.add_argument("--m2l-pair-fill", type=int, default=-1,
                     help="problems whose M2L tiles are less full than this (percent) run M2L pair by pair")
     ap.add_argument("--near-fork", type=int, default=-1,
@@ -267,8 +273,30 @@ def main():
         return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
     precision = args.precision or DEFAULT_PRECISION[args.config]
+    tuning = None
+    if not args.no_autotune:
+        # the layout search times graph replays of this very evaluation; an
+        # explicit --m2l-tile / --near-fork / --m2l-pair-fill is its start
+        from paper_2303_08394_amd import autotune as A
+        ts = torch.cuda.Stream()
+        touts = ([torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs] if batch
+                 else [torch.empty((n_rhs, n), dtype=torch.float64, device=dev)])
+
+        def tune_run():
+            with torch.cuda.stream(ts):
+                evaluate_all(precision, touts)
+
+        t0 = time.perf_counter()
+        tr = A.search(tune_run, ts)
+        tuning = {"chosen": tr.best, "start_ms": tr.start_ms, "best_ms": tr.best_ms,
+                  "trials": len(tr.trials), "search_s": time.perf_counter() - t0}
+        del touts
+    layout = {k: K.get_tuning(k) for k in ("m2l_tile_cols", "m2l_split", "m2l_pair_fill", "near_fork")}
+    default_layout = layout == {"m2l_tile_cols": 64, "m2l_split": 1, "m2l_pair_fill": 40, "near_fork": 4}
     res, t_eager, phases = run(precision, args.steps, args.warmup)
-    result = {"eager_profiled_ms_per_step": t_eager * 1e3}
+    result = {"eager_profiled_ms_per_step": t_eager * 1e3, "layout": layout}
+    if tuning is not None:
+        result["tuning"] = tuning
     t_step = run_graph(precision, args.steps, args.warmup) if not args.no_graph else t_eager
     if not args.no_fp64_leg and precision != "fp64" and args.config != "multi_rhs_1m":
         ref, t64, ph64 = run("fp64", max(2, args.steps // 4), 1)
@@ -353,8 +381,9 @@ def main():
         leaf_rate = leaf_pairs / (ms["far"] / max(launches["far"], 1) * 1e-3)
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
-    roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" else None
-    if args.config == "uniform_1m" and dom == "m2l" and not args.m2l_tile:
+    # the committed counter summaries were taken with the default layout
+    roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" and default_layout else None
+    if args.config == "uniform_1m" and dom == "m2l" and default_layout:
         # SQ_VALU_MFMA_BUSY_CYCLES over the launch's cycles, and the clock the
         # GRBM counter reads meanwhile (rocprofv3, same kernel source)
         roof["mfma_busy_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_mfma_busy_{precision}")

@@ -325,6 +325,12 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  * EINVAL for an unknown key or value. */
 kifmm_status kifmm_set_tuning(const char* key, int32_t value);
 
+/* The value a tuning knob of kifmm_set_tuning currently holds (its default
+ * until it is set), written to *value.  Process-wide, like the knobs; the
+ * autotuner (paper_2303_08394_amd/autotune.py) reads the layout keys before
+ * it searches them.  EINVAL for a null argument or an unknown key. */
+kifmm_status kifmm_get_tuning(const char* key, int32_t* value);
+
 void kifmm_tree_destroy(kifmm_tree* tree);
 void kifmm_ops_destroy(kifmm_ops* ops);
 

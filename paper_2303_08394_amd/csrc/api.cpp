@@ -442,8 +442,46 @@ void kifmm_ops_destroy(kifmm_ops* ops) {
   delete ops;
 }
 
+static kifmm_status set_tuning_impl(const char* key, int32_t value);
+
+// The values of the knobs whose state lives with the evaluation kernels, as
+// last set here (their defaults until then), for kifmm_get_tuning.
+static std::atomic<int> g_near_fork_set{4}, g_graph_set{1}, g_fp64_sum_min_p_set{10},
+    g_check_min_p_set{10}, g_far_fp64_min_p_set{10};
+
+static std::atomic<int>* tuning_slot(const char* key) {
+  static const struct {
+    const char* key;
+    std::atomic<int>* v;
+  } slots[] = {{"m2l_tile_cols", &g_m2l_tile_cols},
+               {"m2l_pair_fill", &g_m2l_pair_fill},
+               {"m2l_split", &g_m2l_split},
+               {"near_fork", &g_near_fork_set},
+               {"graph", &g_graph_set},
+               {"m2l_fp64_sum_min_p", &g_fp64_sum_min_p_set},
+               {"m2l_check_min_p", &g_check_min_p_set},
+               {"far_fp64_min_p", &g_far_fp64_min_p_set}};
+  for (const auto& sl : slots)
+    if (std::strcmp(key, sl.key) == 0) return sl.v;
+  return nullptr;
+}
+
+kifmm_status kifmm_get_tuning(const char* key, int32_t* value) {
+  if (!key || !value) return fail(KIFMM_EINVAL, "get_tuning: null argument");
+  std::atomic<int>* v = tuning_slot(key);
+  if (!v) return fail(KIFMM_EINVAL, std::string("get_tuning: unknown key ") + key);
+  *value = v->load();
+  return KIFMM_OK;
+}
+
 kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
   if (!key) return fail(KIFMM_EINVAL, "set_tuning: null key");
+  const kifmm_status st = set_tuning_impl(key, value);
+  if (st == KIFMM_OK) *tuning_slot(key) = value;
+  return st;
+}
+
+static kifmm_status set_tuning_impl(const char* key, int32_t value) {
   if (std::strcmp(key, "m2l_tile_cols") == 0) {
     if (value != 64 && value != 128 && value != 192)
       return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64, 128 or 192");

@@ -48,7 +48,7 @@ EXPORTED = [
     "kifmm_ops_save", "kifmm_ops_load",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
-    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
+    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
     L.kifmm_get_phase_times.argtypes = [D, C.POINTER(I64)]
     L.kifmm_debug_buffer.argtypes = [P, I32, I32, I32, D, I64]
     L.kifmm_set_tuning.argtypes = [C.c_char_p, I32]
+    L.kifmm_get_tuning.argtypes = [C.c_char_p, C.POINTER(I32)]
     L.kifmm_tree_destroy.argtypes = [P]
     L.kifmm_tree_destroy.restype = None
     L.kifmm_ops_destroy.argtypes = [P]
@@ -385,6 +386,13 @@ def evaluate_simple(src, q, tgt, p: int) -> np.ndarray:
 def set_tuning(key: str, value: int):
     """Process-wide kernel tuning knob (see kifmm_set_tuning)."""
     _check(lib().kifmm_set_tuning(key.encode(), int(value)))
+
+
+def get_tuning(key: str) -> int:
+    """Current value of a tuning knob (see kifmm_get_tuning)."""
+    v = C.c_int32(0)
+    _check(lib().kifmm_get_tuning(key.encode(), C.byref(v)))
+    return int(v.value)
 
 
 def set_profiling(on: bool):
