@@ -47,23 +47,31 @@ class TuneResult:
     from_cache: bool = False
 
 
-def time_ms(run: Callable[[], None], stream, steps: int = 10, warmup: int = 2) -> float:
-    """Mean time of one ``run()`` in ms, between HIP events recorded on
-    ``stream`` (the stream ``run`` launches on).  The warm-up calls absorb
-    plan rebuilds and graph captures that a knob change triggers."""
+def _timed(run: Callable[[], None], stream, n: int) -> float:
     import torch
 
-    for _ in range(warmup):
-        run()
-    stream.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    for _ in range(steps):
+    for _ in range(n):
         run()
     t1.record(stream)
     t1.synchronize()
-    return t0.elapsed_time(t1) / steps
+    return t0.elapsed_time(t1) / n
+
+
+def time_ms(run: Callable[[], None], stream, steps: int = 30, warmup: int = 3, budget_s: float = 0.25) -> float:
+    """Mean time of one ``run()`` in ms, between HIP events recorded on
+    ``stream`` (the stream ``run`` launches on).  The warm-up calls absorb
+    plan rebuilds and graph captures that a knob change triggers; one timed
+    call then sizes the sample to about ``budget_s`` seconds (between 2 and
+    ``steps`` calls), so slow workloads are not timed for minutes."""
+    for _ in range(warmup):
+        run()
+    stream.synchronize()
+    one = _timed(run, stream, 1)
+    n = max(2, min(steps, int(budget_s * 1e3 / max(one, 1e-3))))
+    return _timed(run, stream, n)
 
 
 def _apply(setting: dict, set_: Callable[[str, int], None]):
@@ -72,7 +80,7 @@ def _apply(setting: dict, set_: Callable[[str, int], None]):
 
 
 def search(run: Callable[[], None], stream=None, *, space: Sequence = SPACE, steps: int = 30,
-           warmup: int = 3, min_gain: float = 0.03, confirm: int = 3,
+           warmup: int = 3, budget_s: float = 0.25, min_gain: float = 0.03, confirm: int = 3,
            timer: Optional[Callable[[], float]] = None,
            get: Callable[[str], int] = K.get_tuning, set_: Callable[[str, int], None] = K.set_tuning
            ) -> TuneResult:
@@ -84,12 +92,12 @@ def search(run: Callable[[], None], stream=None, *, space: Sequence = SPACE, ste
     ``confirm`` more times, alternately, and the new one is kept only if its
     median still beats the start's by ``min_gain``.  The kept layout is left
     in force; on an error the starting layout is put back.  ``timer``
-    (default: ``time_ms(run, stream, steps, warmup)``) returns ms per
+    (default: ``time_ms(run, stream, steps, warmup, budget_s)``) returns ms per
     evaluation under the knobs in force."""
     if timer is None:
         if stream is None:
             raise ValueError("search: a stream (the one run() launches on) or a timer is required")
-        timer = lambda: time_ms(run, stream, steps, warmup)  # noqa: E731
+        timer = lambda: time_ms(run, stream, steps, warmup, budget_s)  # noqa: E731
     cur = {k: get(k) for k, _ in space}
     first = dict(cur)
     try:
