@@ -83,10 +83,11 @@ def _profile_value(name: str, key: str):
     return float(kv[key]) if key in kv else None
 
 
-def _measured_traffic(precision: str):
+def _measured_traffic(key: str):
     """HBM bytes per M2L launch (FETCH_SIZE + WRITE_SIZE, scaled by the
-    copy-kernel calibration)."""
-    return _profile_value("m2l_traffic_uniform1m_p6.txt", f"traffic_bytes_{precision}")
+    copy-kernel calibration); key: the precision, with _tileN for M2L tiles
+    of N columns other than 64."""
+    return _profile_value("m2l_traffic_uniform1m_p6.txt", f"traffic_bytes_{key}")
 
 
 # Headline mixed mode: FP32 bulk, FP64 solves and per-target sums, M2L as
@@ -292,7 +293,6 @@ def main():
                   "trials": len(tr.trials), "search_s": time.perf_counter() - t0}
         del touts
     layout = {k: K.get_tuning(k) for k in ("m2l_tile_cols", "m2l_split", "m2l_pair_fill", "near_fork")}
-    default_layout = layout == {"m2l_tile_cols": 64, "m2l_split": 1, "m2l_pair_fill": 40, "near_fork": 4}
     res, t_eager, phases = run(precision, args.steps, args.warmup)
     result = {"eager_profiled_ms_per_step": t_eager * 1e3, "layout": layout}
     if tuning is not None:
@@ -381,13 +381,17 @@ def main():
         leaf_rate = leaf_pairs / (ms["far"] / max(launches["far"], 1) * 1e-3)
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
-    # the committed counter summaries were taken with the default layout
-    roof["traffic"] = _measured_traffic(precision) if args.config == "uniform_1m" and default_layout else None
-    if args.config == "uniform_1m" and dom == "m2l" and default_layout:
+    # the committed counter summaries are per M2L tile width (two parity parts
+    # per tile, gathered tiles: the layouts whose M2L kernel they measured)
+    m2l_counters = (args.config == "uniform_1m" and dom == "m2l" and layout["m2l_split"] == 1
+                    and layout["m2l_pair_fill"] != 101)
+    sfx = precision + ("" if layout["m2l_tile_cols"] == 64 else f"_tile{layout['m2l_tile_cols']}")
+    roof["traffic"] = _measured_traffic(sfx) if m2l_counters else None
+    if m2l_counters:
         # SQ_VALU_MFMA_BUSY_CYCLES over the launch's cycles, and the clock the
         # GRBM counter reads meanwhile (rocprofv3, same kernel source)
-        roof["mfma_busy_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_mfma_busy_{precision}")
-        roof["clock_ghz_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_clock_ghz_{precision}")
+        roof["mfma_busy_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_mfma_busy_{sfx}")
+        roof["clock_ghz_counter"] = _profile_value("m2l_mfma_util_uniform1m_p6.txt", f"m2l_clock_ghz_{sfx}")
 
     if not batch and n_rhs == 1 and not args.no_gradient and not kappa:
         # potentials + gradients (kifmm_evaluate_gradient), graph replays as
