@@ -34,11 +34,15 @@ PEAK_FP64_MFMA = 78.6e12
 PEAK_BF16_MFMA = 2.5e15     # dense BF16 / FP16 matrix FLOP/s
 PEAK_HBM = 8.0e12
 # The particle kernels are bound by plain FP32 VALU issue: 256 CUs x 4 SIMDs x
-# 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s.  One pair interaction issues
-# 9 full-rate instructions (3 sub, mul + 2 fma for r^2, select, fma for the sum)
-# plus one reciprocal square root at quarter rate (4 issue slots): 13 slots.
+# 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s.  The compiled source loop
+# of the leaf kernel issues 37 VALU instructions per four pairs that need no
+# coincidence test (per pair 3 sub, mul + 2 fma for r^2, rsqrt, fma for the
+# sum; plus the loop's own index and bound updates), counted one issue slot
+# each: the rocprofv3 counters show this kernel issuing slightly more than one
+# VALU instruction per 4 clocks per SIMD, so the reciprocal square root does
+# not cost the main pipe more than one slot.  9.25 slots per pair.
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
-SLOTS_PER_PAIR = 13.0
+SLOTS_PER_PAIR = 37.0 / 4.0
 PEAK_PAIRS = VALU_LANE_OPS / SLOTS_PER_PAIR
 
 
