@@ -116,3 +116,20 @@ def test_space_is_valid_for_the_library():
             K.set_tuning(k, cands[0])
     with pytest.raises(K.KifmmError, match="unknown"):
         K.get_tuning("no_such_key")
+
+
+def test_signature_names_the_workload():
+    """The cache key separates workloads by tree shape, order, precision and
+    right-hand sides (host only: no device is needed to form it)."""
+    import numpy as np
+
+    x = np.random.default_rng(0).random((2000, 3))
+    t1 = K.Tree(x, uniform_depth=2, center=(0.5, 0.5, 0.5), halfwidth=0.5)
+    t2 = K.Tree(x, ncrit=32, max_depth=8, center=(0.5, 0.5, 0.5), halfwidth=0.5)
+    o4 = K.Operators(4)
+    o5 = K.Operators(5)
+    keys = {A.signature(t1, o4, "fp32"), A.signature(t2, o4, "fp32"), A.signature(t1, o5, "fp32"),
+            A.signature(t1, o4, "bf16x3"), A.signature(t1, o4, "fp32", n_rhs=4),
+            A.signature(t1, o4, "fp32", what="batch")}
+    assert len(keys) == 6
+    assert A.signature(t1, o4, "fp32") == A.signature(t1, o4, "fp32")
