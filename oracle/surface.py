@@ -44,8 +44,3 @@ def surface_grid(p: int) -> np.ndarray:
                 if a in (0, p - 1) or b in (0, p - 1) or c in (0, p - 1):
                     pts.append((g[a], g[b], g[c]))
     return np.array(pts, dtype=np.float64)
-
-
-def box_surface(p: int, center, halfwidth: float, radius: float) -> np.ndarray:
-    """Surface points of a box: center + radius * halfwidth * s."""
-    return np.asarray(center, dtype=np.float64)[None, :] + (radius * halfwidth) * surface_grid(p)
