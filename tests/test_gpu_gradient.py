@@ -111,3 +111,40 @@ def test_gradient_fullsize_1m():
     print(f"1M gradient bf16x3: rel L2 vs FP64 GPU {e64:.2e}, vs direct (40 targets) {ed:.2e}")
     assert e64 < 2e-5
     assert ed < 5e-5
+
+
+def _sphere300k():
+    """The 300k jittered-sphere twin of the 4M workload (p = 8, n_crit 64) with
+    the oracle's potentials and gradients on 400 sampled targets (stored by
+    tests/golden/make_oracle_samples.py from oracle/ alone)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_oracle_samples as M
+    make_inputs, p, kw, k, _ = M.CASES["sphere300k_nc64_p8"]
+    x, q = make_inputs()
+    d = dict(np.load(M.path("sphere300k_nc64_p8")))
+    assert str(d["inputs_sha"]) == M.inputs_sha(x, np.atleast_2d(q))
+    return x, q, p, kw, d
+
+
+@pytest.mark.xfail(reason="FP32-bulk gradients on a jittered surface measured 2.4e-5 (300k) and 9.4e-5 "
+                          "(4M) against FP64: equivalent densities rounded to FP32 before the leaf stage",
+                   strict=False)
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3"])
+def test_gradient_on_a_jittered_sphere(precision):
+    """Points on a sphere with radial jitter 1e-3: the gradient terms of the
+    equivalent surfaces cancel strongly.  Gate 1e-5 against the FP64 GPU
+    gradient (all targets) and against the oracle's gradient (400 targets)."""
+    x, q, p, kw, d = _sphere300k()
+    tree = K.Tree(x, **kw)
+    got = gpu_grad(tree, p, q, precision)[0]
+    ref = gpu_grad(tree, p, q, "fp64")[0]
+    e64 = rel(got[1:], ref[1:])
+    eo = rel(got[1:, d["idx"]], d["grad"][0])
+    eo64 = rel(ref[1:, d["idx"]], d["grad"][0])
+    print(f"jittered sphere 300k p8 {precision}: gradient vs FP64 GPU {e64:.2e}, vs oracle {eo:.2e} "
+          f"(FP64 GPU vs oracle {eo64:.2e})")
+    assert eo64 < 1e-8
+    assert e64 < 1e-5
+    assert eo < 1e-5
