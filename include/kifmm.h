@@ -261,6 +261,12 @@ kifmm_status kifmm_evaluate_simple(const double* src, const double* q, int64_t n
  * synchronises the stream of the last evaluate. */
 kifmm_status kifmm_set_profiling(int32_t enable);
 int32_t kifmm_n_phases(void);
+/* Number of evaluation graphs captured so far in this process (an evaluate
+ * on a non-default stream captures one when the tree's last graph was made
+ * for another precision, stream, operator set, buffers or tuning, and
+ * replays it otherwise).  An operator set made after another was destroyed
+ * never replays the other's graph, even at the same address.  Never fails. */
+int64_t kifmm_graph_captures(void);
 const char* kifmm_phase_name(int32_t i);
 kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches);
 

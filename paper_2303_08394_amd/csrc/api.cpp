@@ -342,6 +342,7 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
                                         pair_fill(n), max_pairs(n, n_rhs), per_level));
       t->state_n = ops->host->n;
     }
+    check_operand_limits(t->state->host->nbox, n_rhs, n);
     const void* q[1] = {charges};
     void* o[1] = {potentials};
     evaluate_forest(*t->state, *ops->host, const_cast<kifmm_ops*>(ops)->cache, q, o, n_rhs,
@@ -394,6 +395,7 @@ kifmm_status kifmm_evaluate_batch(int32_t n_prob, const kifmm_tree* const* trees
       }
       st = slot.get();
     }
+    check_operand_limits(st->host->nbox, 1, ops->host->n);
     evaluate_forest(*st, *ops->host, const_cast<kifmm_ops*>(ops)->cache, charges, potentials, 1,
                     io_fp64 != 0, precision, hip_stream);
   });
@@ -530,6 +532,7 @@ kifmm_status kifmm_set_profiling(int32_t enable) {
   set_profiling(enable != 0);
   return KIFMM_OK;
 }
+int64_t kifmm_graph_captures(void) { return graph_captures(); }
 int32_t kifmm_n_phases(void) { return n_phases(); }
 const char* kifmm_phase_name(int32_t i) { return phase_name(i); }
 kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches) {

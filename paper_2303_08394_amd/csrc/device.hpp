@@ -96,6 +96,8 @@ void set_far_fp64_min_p(int p);
 void set_m2l_check_min_p(int p);
 // capture evaluations on non-default streams into hipGraphs (default on)
 void set_use_graphs(bool on);
+// evaluation graphs captured so far in this process
+int64_t graph_captures();
 void set_near_fork(int v);
 // smallest order at which FP32-accumulating M2L sums its steps in FP64
 void set_m2l_fp64_sum_min_p(int p);

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -49,8 +50,14 @@ __device__ inline int f16_density_exp(const unsigned* absmax) {
 // device state
 // ------------------------------------------------------------------------
 
+// Every DevOps gets a new generation number: a captured evaluation graph is
+// keyed by it, never by the DevOps address, which a later operator set can
+// reuse after this one is destroyed.
+static std::atomic<uint64_t> g_ops_generation{0};
+
 struct DevOps {
   int n = 0, ld = 0, p = 0;
+  uint64_t generation = ++g_ops_generation;
   // table sets: 1 (Laplace), or one per level (screened kernel, exp(-kappa d)
   // / (4 pi d)); every table below holds `levels` sets back to back
   int levels = 1;
@@ -1432,9 +1439,14 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
   // step ahead (the tile's operator list sits in LDS), so no load latency is
   // exposed when the step changes.  Slots past the tile's columns read the
   // all-zero box.
+  // b_goff counts 16-byte units from the start of the input columns: the
+  // operand of a wide multi-RHS problem passes 2^31 elements (1M points,
+  // p = 10, 64 right-hand sides, split parts: 2.5e9), while 2^32 units of
+  // 16 bytes cover 64 GiB (run_gemm refuses larger operands)
   int ld_st = sb, ld_kc = 0;
   int cur_op = 0, nxt_op = 0;
-  int nxt_src[Cfg::B_PER_T], b_goff[Cfg::B_PER_T];
+  int nxt_src[Cfg::B_PER_T];
+  uint32_t b_goff[Cfg::B_PER_T];
   // The prefetch loads are unconditional (indices clamped into the tile, a
   // step past the end re-reads the last one) so that they land directly in
   // the registers that carry them to the next step; slots past the tile's
@@ -1458,10 +1470,11 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
       b_unit(tid + j * NT, s, t, c);
       s += col0;
       const int box = s < ncols ? nxt_src[j] : a.zero_box;
+      const uint32_t col = uint32_t(box) * uint32_t(a.n_rhs) + uint32_t(s % a.n_rhs);
       if constexpr (Cfg::SPLIT)
-        b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld * NB + t * KC + c * Cfg::EPC;
+        b_goff[j] = col * uint32_t(ld * NB * int(sizeof(TI)) / 16) + uint32_t((t * KC) / Cfg::EPC + c);
       else
-        b_goff[j] = (box * a.n_rhs + s % a.n_rhs) * ld + c * (16 / int(sizeof(TI)));
+        b_goff[j] = col * uint32_t(ld * int(sizeof(TI)) / 16) + uint32_t(c);
     }
   };
   auto load_regs = [&](auto P) __attribute__((always_inline)) {
@@ -1470,9 +1483,9 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
     const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + NA * k0;
 #pragma unroll
     for (int j = 0; j < Cfg::A_PER_T; ++j) ra[R][j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
-    const TI* inb = static_cast<const TI*>(a.in) + (Cfg::SPLIT ? NB * k0 : k0);
+    const u32x4* inb = reinterpret_cast<const u32x4*>(static_cast<const TI*>(a.in) + (Cfg::SPLIT ? NB * k0 : k0));
 #pragma unroll
-    for (int j = 0; j < Cfg::B_PER_T; ++j) rb[R][j] = *reinterpret_cast<const u32x4*>(inb + b_goff[j]);
+    for (int j = 0; j < Cfg::B_PER_T; ++j) rb[R][j] = inb[b_goff[j]];
   };
   auto advance = [&]() __attribute__((always_inline)) {
     if (++ld_kc == kcs) {
@@ -1734,6 +1747,15 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
 // pipeline
 // ------------------------------------------------------------------------
 
+// 16-byte units spanned by the input columns of a gathered GEMM (boxes
+// 0..zero_box, n_rhs columns each of ld rows, split modes NB parts a row)
+template <int MODE, class TI>
+uint64_t gemm_in_units(int64_t zero_box, int64_t n_rhs, int64_t ld) {
+  using Cfg = GemmCfg<MODE, TI, float, 1, 1, kRB>;
+  const uint64_t parts = Cfg::SPLIT ? uint64_t(Cfg::NB) : 1u;
+  return uint64_t(zero_box + 1) * uint64_t(n_rhs) * uint64_t(ld) * parts * sizeof(TI) / 16;
+}
+
 // zero_box: the forest's box count; the columns of that box in every buffer
 // are allocated, zero, and never written.
 template <int MODE, class TI, class TO, int TAG = 0>
@@ -1745,6 +1767,9 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   if (ncols > 192) raise(KIFMM_EUNSUPPORTED, "plan width exceeds the GEMM tile");
   if (ld % 32) raise(KIFMM_EINVAL, "operator leading dimension must be a multiple of 32");
   if (P.max_tile_steps > kMaxTileSteps) raise(KIFMM_EUNSUPPORTED, "GEMM tile with too many operator steps");
+  // the kernel addresses its input columns in 32-bit counts of 16-byte units
+  if (gemm_in_units<MODE, TI>(zero_box, n_rhs, ld) > (uint64_t(1) << 32))
+    raise(KIFMM_EUNSUPPORTED, "GEMM operand beyond 64 GiB (boxes x right-hand sides x rows)");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
   dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
@@ -2117,6 +2142,7 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
 // Evaluations on a non-default stream are captured once into a hipGraph and
 // replayed with one launch while the inputs of the capture stay the same.
 static bool g_use_graphs = true;
+static std::atomic<int64_t> g_graph_captures{0};  // evaluation graphs captured so far
 void set_use_graphs(bool on) { g_use_graphs = on; }
 
 void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const void* const* charges,
@@ -2163,7 +2189,8 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   // everything the captured launches depend on
   std::vector<const void*> key = {reinterpret_cast<const void*>(intptr_t(prec)),
                                   reinterpret_cast<const void*>(intptr_t(n_rhs)),
-                                  reinterpret_cast<const void*>(intptr_t(io_fp64)), s, O, W,
+                                  reinterpret_cast<const void*>(intptr_t(io_fp64)), s,
+                                  reinterpret_cast<const void*>(uintptr_t(O->generation)), W,
                                   reinterpret_cast<const void*>(intptr_t(g_far_fp64_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_check_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p)),
@@ -2195,9 +2222,12 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
       raise(KIFMM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
     }
     F.graph_key = key;
+    ++g_graph_captures;
   }
   HIPCHECK(hipGraphLaunch(F.graph, s));
 }
+
+int64_t graph_captures() { return g_graph_captures.load(); }
 
 void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out) {
   if (!st.forest) raise(KIFMM_EINVAL, "debug_buffer: no evaluation has run on this tree");

@@ -52,6 +52,14 @@ Plan new_plan(int TB) {
 
 }  // namespace
 
+void check_operand_limits(int64_t nbox, int n_rhs, int n) {
+  const int64_t ld = (int64_t(n) + 31) / 32 * 32;
+  // widest element of a column: three 16-bit parts (6 bytes) or FP64 (8)
+  const int64_t bytes = (nbox + 1) * int64_t(n_rhs) * ld * 8;
+  if (nbox < 0 || n_rhs < 1 || n < 1 || bytes / 16 > (int64_t(1) << 32))
+    raise(KIFMM_EUNSUPPORTED, "evaluate: density columns beyond 64 GiB (boxes x right-hand sides x operator rows)");
+}
+
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
                          bool split, double pair_fill, int64_t max_pairs, bool per_level) {
   auto* Fp = new HostForest();

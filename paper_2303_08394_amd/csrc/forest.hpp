@@ -88,4 +88,11 @@ struct HostForest {
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
                          bool split, double pair_fill, int64_t max_pairs, bool per_level = false);
 
+// Raises KIFMM_EUNSUPPORTED unless the density columns of a forest of nbox
+// boxes (plus the zero box) with n_rhs right-hand sides at operator size n,
+// split into up to three 16-bit parts or held in FP64, span at most 2^32
+// units of 16 bytes (64 GiB): the gathered GEMM addresses them with 32-bit
+// unit offsets.
+void check_operand_limits(int64_t nbox, int n_rhs, int n);
+
 }  // namespace kifmm

@@ -348,6 +348,18 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
         T.c0[d] = prm.root_center[d];
       }
       T.r0 = prm.root_halfwidth;
+      // a point outside the given root cube would be clamped into a boundary
+      // leaf, beyond that leaf's equivalent surface: refused
+      auto inside = [&](const double* x, int64_t n) {
+        for (int64_t i = 0; i < n; ++i)
+          for (int d = 0; d < 3; ++d) {
+            const double t = (x[3 * i + d] - (T.c0[d] - T.r0)) / (2.0 * T.r0);
+            if (!(t >= 0.0 && t <= 1.0)) return false;
+          }
+        return true;
+      };
+      if (!inside(src, nsrc) || !inside(tgt, ntgt))
+        raise(KIFMM_EINVAL, "build_tree: a point lies outside the given root box");
     } else {
       double mn[3], mx[3];
       for (int d = 0; d < 3; ++d) mn[d] = mx[d] = src[d];

@@ -52,16 +52,21 @@ struct Frame {
   int L;      // key level
 };
 
+// A point outside the closed root cube (t outside [0, 1] on some axis, or
+// not a number) is counted in *outside: the update is then refused, as the
+// clamp would put it in a boundary leaf beyond that leaf's equivalent surface.
 __global__ void key_kernel(const double* __restrict__ xyz, int64_t n, Frame f, u64* __restrict__ keys,
-                           int32_t* __restrict__ idx) {
+                           int32_t* __restrict__ idx, unsigned long long* __restrict__ outside) {
 #pragma clang fp contract(off)
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double cells = double(int64_t(1) << f.L), maxi = cells - 1.0;
   u64 ix[3];
+  bool inside = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double t = (xyz[3 * i + d] - f.lo[d]) / (2.0 * f.r0);
+    inside = inside && t >= 0.0 && t <= 1.0;
     double c = floor(t * cells);
     if (!(c >= 0.0)) c = 0.0;
     if (c > maxi) c = maxi;
@@ -69,6 +74,7 @@ __global__ void key_kernel(const double* __restrict__ xyz, int64_t n, Frame f, u
   }
   keys[i] = morton3(ix[0], ix[1], ix[2]);
   idx[i] = int32_t(i);
+  if (!inside) atomicAdd(outside, 1ull);
 }
 
 // Digit counts of each block's tile, stored digit-major: hist[digit][block].
@@ -279,7 +285,7 @@ struct PendingPoints {
   u64* k0 = nullptr;
   int32_t* v0 = nullptr;
   uint32_t *hist = nullptr, *totals = nullptr;
-  unsigned long long* stat = nullptr;  // [4]: flag, source count, target count
+  unsigned long long* stat = nullptr;  // [4]: flag, source count, target count, points outside the root
   SortedSet src[2], tgt[2];
   int cur = -1;             // output set of the last accepted update
   bool stale_host = false;  // the host copy of the tree lags set `cur`
@@ -345,7 +351,7 @@ static void sort_set(PendingPoints& P, const HostTree& T, const double* xyz, int
   f.r0 = T.r0;
   f.L = T.key_level;
   const unsigned grid = unsigned((n + 255) / 256);
-  hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, P.k0, P.v0);
+  hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, P.k0, P.v0, P.stat + 3);
   LAUNCHCHECK("key_kernel");
   const int nblk = int((n + kTile - 1) / kTile);
   const int64_t m = int64_t(kThreads) * nblk;  // scanned entries
@@ -410,6 +416,9 @@ void update_points_device(PendingPoints& P, const HostTree& T, EvalState* st, co
   unsigned long long stat[4];
   HIPCHECK(hipMemcpyAsync(stat, P.stat, sizeof(stat), hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));
+  if (stat[3] != 0)
+    raise(KIFMM_EINVAL, "update_points: " + std::to_string(stat[3]) +
+                            " point(s) outside the tree's root box (rebuild the tree on the host)");
   if ((stat[0] & 0xffffffffull) != 0 || int64_t(stat[1]) != T.nsrc || (tgt && int64_t(stat[2]) != T.ntgt))
     raise(KIFMM_EINVAL,
           "update_points: the points occupy other leaves than the tree's (rebuild the tree on the host)");

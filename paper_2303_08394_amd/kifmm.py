@@ -48,7 +48,7 @@ EXPORTED = [
     "kifmm_ops_save", "kifmm_ops_load",
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
-    "kifmm_get_phase_times", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
+    "kifmm_get_phase_times", "kifmm_graph_captures", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
 
 
@@ -89,6 +89,8 @@ def lib():
     L.kifmm_phase_name.argtypes = [I32]
     L.kifmm_phase_name.restype = C.c_char_p
     L.kifmm_get_phase_times.argtypes = [D, C.POINTER(I64)]
+    L.kifmm_graph_captures.argtypes = []
+    L.kifmm_graph_captures.restype = I64
     L.kifmm_debug_buffer.argtypes = [P, I32, I32, I32, D, I64]
     L.kifmm_set_tuning.argtypes = [C.c_char_p, I32]
     L.kifmm_get_tuning.argtypes = [C.c_char_p, C.POINTER(I32)]
@@ -99,6 +101,7 @@ def lib():
     L.kifmm_last_error.restype = C.c_char_p
     for name in EXPORTED:
         if name not in ("kifmm_ops_n", "kifmm_n_phases", "kifmm_phase_name", "kifmm_last_error",
+                        "kifmm_graph_captures",
                         "kifmm_tree_destroy", "kifmm_ops_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
@@ -397,6 +400,11 @@ def get_tuning(key: str) -> int:
 
 def set_profiling(on: bool):
     _check(lib().kifmm_set_profiling(1 if on else 0))
+
+
+def graph_captures() -> int:
+    """Evaluation graphs captured so far in this process."""
+    return int(lib().kifmm_graph_captures())
 
 
 def phase_times() -> dict:

@@ -127,6 +127,27 @@ int main() {
     CHECK(threw);
   }
 
+  // density columns the GEMM can address with 32-bit counts of 16-byte units
+  {
+    auto refused = [](int64_t nbox, int n_rhs, int n) {
+      try {
+        check_operand_limits(nbox, n_rhs, n);
+      } catch (const Error& e) {
+        return e.status == KIFMM_EUNSUPPORTED;
+      }
+      return false;
+    };
+    // 1M points at depth 5 (37,449 boxes), p = 10 (n = 488), 64 right-hand
+    // sides: 2.5e9 split elements, past 2^31, but 1.2e9 units of 16 bytes
+    CHECK(!refused(37449, 64, 488));
+    // p = 16 (n = 1352, ld = 1376), 64 right-hand sides: the largest box
+    // count that fits, and one more
+    const int64_t ld16 = 1376, cap = (int64_t(1) << 36) / (64 * ld16 * 8) - 1;
+    CHECK(!refused(cap, 64, 1352));
+    CHECK(refused(cap + 1, 64, 1352));
+    CHECK(refused(-1, 1, 152) && refused(10, 0, 152));
+  }
+
   // operators, the cache file and its rejections
   std::unique_ptr<HostOps> ops(build_host_ops(4, 1e-9));
   const std::string path = "host_sanitize_ops.bin";

@@ -106,6 +106,25 @@ def test_points_on_faces_and_duplicates():
     _compare_trees(ot, ct)
 
 
+def test_points_outside_a_given_root_are_refused():
+    """With a given root box a point outside the closed cube would be clamped
+    into a boundary leaf (beyond its equivalent surface): refused.  Points on
+    the closed faces are inside."""
+    x = np.random.default_rng(3).random((100, 3))
+    for bad in (1.0 + 1e-12, -1e-15, 2.0):
+        y = x.copy()
+        y[17, 2] = bad
+        with pytest.raises(K.KifmmError, match="outside the given root box"):
+            K.Tree(y, uniform_depth=2, **CUBE)
+        with pytest.raises(K.KifmmError, match="outside the given root box"):
+            K.Tree(x, y, ncrit=8, max_depth=6, **CUBE)
+    y = x.copy()
+    y[0] = (0.0, 1.0, 1.0)
+    assert K.Tree(y, uniform_depth=2, **CUBE).info().n_src == 100
+    # the derived root always holds every point
+    assert K.Tree(3.0 * y - 7.0, ncrit=8, max_depth=6).info().n_src == 100
+
+
 def test_jacobi_svd_pinv_matches_library():
     s = surface_grid(6)
     for p in (2, 4, 6):

@@ -209,6 +209,40 @@ def test_graph_replays_match_eager():
             K.set_tuning("graph", 1)
 
 
+def test_new_operator_set_is_captured_anew():
+    """An evaluation with a new operator set of the same order, made after
+    the old one was destroyed (its tables freed, its address free for
+    reuse), captures a new graph instead of replaying one that points at the
+    freed tables; results equal the first evaluation bitwise."""
+    x, q = I.uniform_cube(6000, seed=32, charge_range=(-1, 1))
+    tree = K.Tree(x, uniform_depth=3, **CUBE)
+    s = torch.cuda.Stream()
+    qd = torch.as_tensor(np.atleast_2d(q), dtype=torch.float64, device=DEV)
+    out = torch.empty_like(qd)
+    with torch.cuda.stream(s):
+        a = K.Operators(4)
+        K.evaluate(tree, a, qd, precision="fp32", out=out)
+        s.synchronize()
+        first = out.cpu().numpy().copy()
+        n0 = K.graph_captures()
+        K.evaluate(tree, a, qd, precision="fp32", out=out)  # replay, no capture
+        s.synchronize()
+        assert K.graph_captures() == n0
+        del a
+        import gc
+        gc.collect()
+        for _ in range(3):
+            b = K.Operators(4)
+            out.zero_()
+            K.evaluate(tree, b, qd, precision="fp32", out=out)
+            s.synchronize()
+            assert K.graph_captures() == n0 + 1
+            np.testing.assert_array_equal(out.cpu().numpy(), first)
+            del b
+            gc.collect()
+            n0 += 1
+
+
 def test_batch_graph_replays_match_eager():
     probs = [I.clustered(n, seed=40 + n) for n in (3000, 5000, 2000)]
     trees = [K.Tree(xx, ncrit=32, max_depth=10, **CUBE) for xx, _ in probs]

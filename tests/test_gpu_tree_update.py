@@ -137,6 +137,29 @@ def test_update_rejects_other_leaves_and_keeps_tree():
     np.testing.assert_array_equal(evaluate(tree, q, p), before)
 
 
+def test_update_rejects_points_outside_the_root_and_keeps_tree():
+    """A point moved past the root cube would be clamped into a boundary
+    leaf, outside that leaf's equivalent surface: the update is refused and
+    the tree evaluates as before."""
+    n, depth, p = 20000, 3, 4
+    x0, q = I.uniform_cube(n, seed=91)
+    tree = K.Tree(x0, uniform_depth=depth, **CUBE)
+    before = evaluate(tree, q, p)
+    for bad_value in (1.0 + 1e-9, -1e-12):
+        moved = x0.copy()
+        moved[123, 1] = bad_value
+        with pytest.raises(K.KifmmError, match="outside the tree's root box"):
+            tree.update_points(dev(moved))
+        np.testing.assert_array_equal(evaluate(tree, q, p), before)
+    # the auto root (bounding cube with a 2^-20 margin) of an adaptive tree
+    tree2 = K.Tree(x0, ncrit=64, max_depth=8)
+    inf = tree2.info()
+    moved = x0.copy()
+    moved[7, 0] = inf.root_center[0] + 1.01 * inf.root_halfwidth
+    with pytest.raises(K.KifmmError, match="outside the tree's root box"):
+        tree2.update_points(dev(moved))
+
+
 def test_update_fullsize_1m():
     """1M points, depth 5: the device sort agrees with the host build."""
     prob = I.uniform_1m()
