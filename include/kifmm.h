@@ -228,8 +228,11 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops,
  * near field) also applies the kernel's derivative to the same densities and
  * charges.  out: DEVICE [n_rhs][4][n_tgt] (caller order): component 0 the
  * potential, 1..3 d/dx, d/dy, d/dz; FP64 if io_fp64 != 0, else FP32.  Other
- * arguments, stream semantics and errors as kifmm_evaluate.  The potential
- * component equals kifmm_evaluate's result to rounding. */
+ * arguments, stream semantics and errors as kifmm_evaluate.  In the FP32-bulk
+ * precisions the downward pass runs L2L and DC2E in FP64 here (the gradient
+ * amplifies FP32 rounding noise on the downward check surface): the potential
+ * component then agrees with kifmm_evaluate's result to that mode's accuracy,
+ * in FP64 to rounding. */
 kifmm_status kifmm_evaluate_gradient(const kifmm_tree* tree, const kifmm_ops* ops,
                                      const void* charges, int32_t n_rhs, void* out,
                                      int32_t io_fp64, kifmm_precision precision,

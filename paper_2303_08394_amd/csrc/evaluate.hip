@@ -86,6 +86,9 @@ struct DevWork {
   void* up_eq = nullptr;
   void* dn_chk = nullptr;
   void* dn_eq = nullptr;
+  // FP32-bulk gradient evaluations: the downward check potentials in FP64
+  // from L2L on (see pipeline)
+  double* dn_chk64 = nullptr;
   double* pot = nullptr;    // [n_rhs][ntgt]
   unsigned* absmax = nullptr;  // [4] scratch word for the FP16 density scale
   size_t col_bytes = 0;
@@ -343,6 +346,7 @@ static uint16_t* upload_split16(DevOps* O, const std::vector<double>& pad) {
 // M2L operand: FP64, FP32, BF16 split or FP16 split, in density or check form.
 struct OpsNeed {
   bool bulk64 = false, m2l64 = false, m2l32 = false, bf16 = false, f16 = false, check_form = false;
+  bool l2l64 = false;  // FP64 L2L in an FP32-bulk evaluation (gradients)
 };
 
 static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const OpsNeed& need) {
@@ -361,10 +365,10 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
       for (int d = 0; d < 3; ++d) s4[4 * i + d] = H.surf[3 * i + d];
     O->surf = dev_upload<double4>(O->allocs, s4);
   }
-  if (need.bulk64 && !O->m2m64) {
+  if (need.bulk64 && !O->m2m64)
     O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8 * H.levels, H.n, O->ld));
+  if ((need.bulk64 || need.l2l64) && !O->l2l64)
     O->l2l64 = dev_upload<double>(O->allocs, pad_table<double>(H.l2l, 8 * H.levels, H.n, O->ld));
-  }
   if (!need.bulk64 && !O->m2m32) {
     O->m2m32 = dev_upload<float>(O->allocs, pad_table<float>(H.m2m, 8 * H.levels, H.n, O->ld));
     O->l2l32 = dev_upload<float>(O->allocs, pad_table<float>(H.l2l, 8 * H.levels, H.n, O->ld));
@@ -417,6 +421,7 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs, bool grad = false) 
   W->dn_chk = alloc_bytes(W->col_bytes);
   W->dn_eq = alloc_bytes(W->col_bytes);
   W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * (grad ? 4 : 1) * F.ntgt * 8));
+  if (grad && !fp64) W->dn_chk64 = static_cast<double*>(alloc_bytes(cols * 8));
   W->absmax = static_cast<unsigned*>(alloc_bytes(16));
   return W;
 }
@@ -668,6 +673,12 @@ __global__ void m2m_sum_kernel(const int32_t* __restrict__ tab, int npar, int64_
 #pragma unroll
   for (int e = 0; e < E; ++e) y[e] = acc[e];
   out[int64_t(t[0]) * units_per_box + u] = r;
+}
+
+// FP32 -> FP64 copy of n values (grid-stride)
+__global__ void widen_kernel(const float* __restrict__ in, double* __restrict__ out, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    out[i] = double(in[i]);
 }
 
 __global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
@@ -2098,14 +2109,37 @@ static void pipeline(DevForest& F, DevOps& O, DevWork& W, const void* const* cha
     a.out_col = dn_chk;
     run_p2p_rc<T, MODE_P2L, 64>(a, F.n_x, n_rhs, false, s, ps);
   }
+  // Gradients in the FP32-bulk modes: from here on the downward check
+  // potentials are FP64 (M2L and P2L added into the FP32 columns above; L2L
+  // runs in FP64 and adds into the FP64 copy; DC2E reads it).  Gradients of
+  // the leaf stage amplify rounding noise on the check surface: a check
+  // potential stored in FP32 alone moves the gradient of points near a
+  // jittered surface by ~3e-6, the FP32 L2L sums by ~2e-5.
+  const bool down64 = sizeof(T) == 4 && W.dn_chk64 != nullptr;
+  if (down64) {
+    PhaseScope ps(PH_L2L, s);
+    const int64_t nv = int64_t(W.col_bytes / sizeof(T));
+    hipLaunchKernelGGL(widen_kernel, dim3(2048), dim3(256), 0, s, reinterpret_cast<const float*>(dn_chk),
+                       W.dn_chk64, nv);
+    LAUNCHCHECK("widen_kernel");
+    ps.launches++;
+  }
   for (int l = 2; l <= F.depth; ++l) {
     if (l >= 3) {
       PhaseScope ps(PH_L2L, s);
-      run_gemm<GF, T, T>(F.l2l[l], l2l + set(l) * 8 * nn, nn, ld, F.nbox, n_rhs, dn_eq, dn_chk, true, s, ps);
+      if (down64)
+        run_gemm<GM_F64, T, double>(F.l2l[l], O.l2l64 + set(l) * 8 * nn, nn, ld, F.nbox, n_rhs, dn_eq,
+                                    W.dn_chk64, true, s, ps);
+      else
+        run_gemm<GF, T, T>(F.l2l[l], l2l + set(l) * 8 * nn, nn, ld, F.nbox, n_rhs, dn_eq, dn_chk, true, s, ps);
     }
     {
       PhaseScope ps(PH_DC2E, s);
-      run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e + set(l) * nn, 0, ld, F.nbox, n_rhs, dn_chk, dn_eq, false, s, ps);
+      if (down64)
+        run_gemm<GM_F64, double, T>(F.dc2e[l], O.dc2e + set(l) * nn, 0, ld, F.nbox, n_rhs, W.dn_chk64, dn_eq,
+                                    false, s, ps);
+      else
+        run_gemm<GM_F64, T, T>(F.dc2e[l], O.dc2e + set(l) * nn, 0, ld, F.nbox, n_rhs, dn_chk, dn_eq, false, s, ps);
     }
   }
   {
@@ -2164,6 +2198,7 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
   need.f16 = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3;
   // folded check form for the FP32 / FP16 M2L operands at high order
   need.check_form = (need.m2l32 || need.f16) && hops.p >= g_m2l_check_min_p && hops.kernel == 0;
+  need.l2l64 = grad && !fp64;
   DevOps* O = ops_for_device(oc, hops, dev, need);
   DevForest& F = *st.forest;
   if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate: operator order differs from the cached forest");

@@ -71,10 +71,12 @@ def test_gradient_vs_oracle(name, precision):
     print(f"{name} {precision}: potential {e_pot:.2e}, gradient {e_grad:.2e}")
     assert e_grad < TOL[precision]
     assert e_pot < (1e-8 if precision == "fp64" else 1e-5)
-    # the potential component is the potential path's, to rounding
+    # the potential component is the potential path's: to rounding in FP64;
+    # the FP32-bulk modes run the downward pass of gradient evaluations in
+    # FP64 from L2L on, so there the two differ by the FP32 path's own error
     plain = K.evaluate(tree, ops(p), torch.as_tensor(q, dtype=torch.float64, device=DEV), precision=precision)
     torch.cuda.synchronize()
-    assert rel(got[:, 0], plain.cpu().numpy()) < (1e-14 if precision == "fp64" else 1e-6)
+    assert rel(got[:, 0], plain.cpu().numpy()) < (1e-14 if precision == "fp64" else 1e-5)
 
 
 def test_gradient_multi_rhs_columns_and_graph_replays():
@@ -128,14 +130,16 @@ def _sphere300k():
     return x, q, p, kw, d
 
 
-@pytest.mark.xfail(reason="FP32-bulk gradients on a jittered surface measured 2.4e-5 (300k) and 9.4e-5 "
-                          "(4M) against FP64: equivalent densities rounded to FP32 before the leaf stage",
-                   strict=False)
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3"])
 def test_gradient_on_a_jittered_sphere(precision):
-    """Points on a sphere with radial jitter 1e-3: the gradient terms of the
-    equivalent surfaces cancel strongly.  Gate 1e-5 against the FP64 GPU
-    gradient (all targets) and against the oracle's gradient (400 targets)."""
+    """Points on a sphere with radial jitter 1e-3, where the leaf stage's
+    gradient amplifies rounding noise on the downward check surface (FP32
+    check potentials alone moved it by 2.4e-5 here, 9.4e-5 on the 4M sphere):
+    the FP32-bulk modes run L2L and DC2E of gradient evaluations in FP64.
+    Gates 1e-5 against the FP64 GPU gradient (all targets) and against the
+    oracle's gradient (400 targets); the FP64 GPU gradient meets the oracle
+    at 1e-7 (at p = 8 the two sides' pseudo-inverses, from different SVD
+    drivers, agree to ~1.5e-8 relative; measured 2.1e-8)."""
     x, q, p, kw, d = _sphere300k()
     tree = K.Tree(x, **kw)
     got = gpu_grad(tree, p, q, precision)[0]
@@ -145,6 +149,6 @@ def test_gradient_on_a_jittered_sphere(precision):
     eo64 = rel(ref[1:, d["idx"]], d["grad"][0])
     print(f"jittered sphere 300k p8 {precision}: gradient vs FP64 GPU {e64:.2e}, vs oracle {eo:.2e} "
           f"(FP64 GPU vs oracle {eo64:.2e})")
-    assert eo64 < 1e-8
+    assert eo64 < 1e-7
     assert e64 < 1e-5
     assert eo < 1e-5
