@@ -125,32 +125,59 @@ def _problems(args):
     raise SystemExit(f"unknown config {args.config}")
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline():
-    """The FP64 oracle on one BLAS thread (its fastest setting: its BLAS calls
-    are small, and 8 threads made it 3.5x slower), on a bounded sample of the
-    same recipe: N = 125,000 uniform-cube points with uniform depth 4 (the
-    same ~30.5 points per leaf and p = 6 as the 1M workload)."""
+    """The FP64 oracle as it stands, on a bounded sample of the same recipe:
+    N = 125,000 uniform-cube points with uniform depth 4 (the same ~30.5
+    points per leaf and p = 6 as the 1M workload), timed twice on this host:
+    with one BLAS thread and with BLAS threads on every core the process may
+    use (len(os.sched_getaffinity(0))); its BLAS calls are small per-box
+    products, so more threads do not help it.  `value` is the faster of the
+    two, `cores` the threads that run used.  Beside it, the direct sum of
+    Eq. (1) (the O(N^2) oracle) timed on all targets of the 20k workload."""
     from threadpoolctl import threadpool_limits
 
+    from oracle import direct
     from oracle import kifmm as OK
     from oracle.octree import Octree
     from paper_2303_08394_amd import inputs as I
-    n, reps = 125_000, 3
-    cores = 1
+    n = 125_000
+    avail = len(os.sched_getaffinity(0))
     x, q = I.uniform_cube(n, seed=0, charge_range=(-1.0, 1.0))
-    with threadpool_limits(limits=cores):
-        t0 = time.perf_counter()
-        tree = Octree(x, x, uniform_depth=4, center=I.UNIT_CUBE_CENTER, halfwidth=I.UNIT_CUBE_HALFWIDTH)
-        fm = OK.KIFMM(tree, 6)
-        t1 = time.perf_counter()
-        for _ in range(reps):
-            fm.evaluate(q[0])
-        t2 = time.perf_counter()
-    ev = (t2 - t1) / reps
-    return {"value": n / ev / 1e6, "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle evaluate, N={n} uniform cube, depth 4 (30.5 pts/leaf), "
-                      f"p=6, {cores} BLAS thread; {reps} evaluations, {ev:.1f} s each "
-                      f"(tree+lists+operators {t1 - t0:.1f} s, not counted)"}
+    t0 = time.perf_counter()
+    tree = Octree(x, x, uniform_depth=4, center=I.UNIT_CUBE_CENTER, halfwidth=I.UNIT_CUBE_HALFWIDTH)
+    fm = OK.KIFMM(tree, 6)
+    fm.evaluate(q[0], sample=np.arange(1))  # forms the operators (setup, not timed)
+    t_setup = time.perf_counter() - t0
+    runs = {}
+    for threads, reps in ((1, 1), (avail, 1)):
+        with threadpool_limits(limits=threads):
+            ta = time.perf_counter()
+            for _ in range(reps):
+                fm.evaluate(q[0])
+            runs[threads] = (time.perf_counter() - ta) / reps
+    best = min(runs, key=runs.get)
+    c1 = I.plain_fp64_20k()
+    ta = time.perf_counter()
+    direct.direct(c1.points, c1.charges[0], c1.points)
+    t_o1 = time.perf_counter() - ta
+    return {"value": n / runs[best] / 1e6, "unit": "Mpoints/s", "cores": best, "kind": "oracle",
+            "sample": f"FP64 oracle evaluate, N={n} uniform cube, depth 4 (30.5 pts/leaf), p=6; "
+                      f"{runs[1]:.1f} s on 1 BLAS thread, {runs[avail]:.1f} s on {avail} "
+                      f"(setup {t_setup:.1f} s, not counted)",
+            "host_cores_available": avail, "cpu_model": _cpu_model(),
+            "evaluate_s_by_threads": {str(k): v for k, v in runs.items()},
+            "direct_sum_20k_all_targets_s": t_o1,
+            "direct_sum_20k_Mpairs_per_s": c1.n * (c1.n - 1) / t_o1 / 1e6}
 
 
 def main():
@@ -318,8 +345,11 @@ def main():
         result["rel_l2_vs_fp64_gpu"] = rel(res[0], ref[0])
     # direct sum on a seeded sample of targets (first problem, first charge vector)
     idx = I.sample_indices(n, args.direct_sample)
+    ta = time.perf_counter()
     exact = direct.direct(prob.points, prob.charges[0], prob.points[idx], kappa=kappa)
+    t_direct = time.perf_counter() - ta
     result["rel_l2_vs_direct_sample"] = rel(res[0][0][idx], exact)
+    result["direct_sample"] = {"targets": int(len(idx)), "cpu_s": t_direct}
     if args.config == "plain_20k":
         from oracle import kifmm as OK
         from oracle.octree import Octree
