@@ -222,6 +222,28 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops,
                             int32_t io_fp64, kifmm_precision precision,
                             void* hip_stream);
 
+/* kifmm_evaluate for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It calls no hipMalloc, hipFree or allocating library routine: every work
+ * buffer of the evaluation (gathered charges, check potentials, equivalent
+ * densities, split M2L operand, pair products, FP64 sums) is carved from a
+ * fixed device array of 256 MiB that each GPU running the library holds until
+ * the process ends, and the kernels are launched eagerly on hip_stream (no
+ * graph of its own, so a caller may capture the call).  Same arguments,
+ * layouts, ownership and results (bitwise) as kifmm_evaluate.
+ * Preconditions: one kifmm_evaluate of (tree, ops, n_rhs, precision) on the
+ * current device since the tree, its points (kifmm_tree_update_points) or
+ * the tuning last changed, so that the tree's device state and the operator
+ * tables are resident; otherwise EINVAL.  EUNSUPPORTED if the work buffers
+ * exceed 256 MiB (the message gives the size needed; 1M points at p = 6 in
+ * the FP32-bulk modes need ~140 MiB); EINVAL while phase profiling is on.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller. */
+kifmm_status kifmm_evaluate_noalloc(const kifmm_tree* tree, const kifmm_ops* ops,
+                                    const void* charges, int32_t n_rhs, void* potentials,
+                                    int32_t io_fp64, kifmm_precision precision,
+                                    void* hip_stream);
+
 /* Potentials and their gradients at the targets (the derivative of Eq. (1)
  * in the target position; the paper evaluates potentials only).  The
  * multipole passes are those of kifmm_evaluate; the leaf stage (L2P, M2P,

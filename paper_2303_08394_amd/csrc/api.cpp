@@ -358,6 +358,29 @@ kifmm_status kifmm_evaluate(const kifmm_tree* tree, const kifmm_ops* ops, const 
   return evaluate_impl(tree, ops, charges, n_rhs, potentials, io_fp64, precision, hip_stream, false);
 }
 
+kifmm_status kifmm_evaluate_noalloc(const kifmm_tree* tree, const kifmm_ops* ops, const void* charges,
+                                    int32_t n_rhs, void* potentials, int32_t io_fp64,
+                                    kifmm_precision precision, void* hip_stream) {
+  return guard([&] {
+    check_eval_args(tree, ops, n_rhs, precision);
+    if (!charges || !potentials) raise(KIFMM_EINVAL, "evaluate_noalloc: null charges or potentials");
+    auto* t = const_cast<kifmm_tree*>(tree);
+    const int n = ops->host->n;
+    check_kernel(*t->host, *ops->host);
+    // the forest (plans and device arrays) must be the one kifmm_evaluate
+    // would use now: building another allocates
+    if (!t->state || t->state_n != n ||
+        !plan_current(*t->state->host, plan_width(n_rhs), m2l_plan_width(n_rhs), n, n_rhs, ops->host->kernel != 0))
+      raise(KIFMM_EINVAL, "evaluate_noalloc: no evaluation state for these operators, right-hand sides and "
+                          "tuning (run kifmm_evaluate once)");
+    if (pending_stale(t->sort) && dev_point_view(*t->state).device != current_device())
+      raise(KIFMM_EINVAL, "evaluate_noalloc: updated points are not on this device (run kifmm_evaluate once)");
+    check_operand_limits(t->state->host->nbox, n_rhs, n);
+    evaluate_forest_noalloc(*t->state, *ops->host, const_cast<kifmm_ops*>(ops)->cache, charges, potentials,
+                            n_rhs, io_fp64 != 0, precision, hip_stream);
+  });
+}
+
 kifmm_status kifmm_evaluate_gradient(const kifmm_tree* tree, const kifmm_ops* ops,
                                      const void* charges, int32_t n_rhs, void* out,
                                      int32_t io_fp64, kifmm_precision precision,

@@ -2,6 +2,7 @@
 // the work buffers, and the entry into the evaluation pipeline.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -45,6 +46,16 @@ struct OpsCache {
 void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& ocache,
                      const void* const* charges, void* const* potentials, int n_rhs,
                      bool io_fp64, kifmm_precision prec, void* stream, bool grad = false);
+
+// Bytes of the allocation-free entry point's work-buffer array on each device.
+constexpr size_t kNoAllocScratchBytes = size_t(256) << 20;
+
+// The evaluation of one tree with every work buffer taken from a fixed
+// device array (kifmm_evaluate_noalloc): no device allocation, eager
+// launches on `stream`.  The tree's device state and the operator tables of
+// `prec` must already be on the current device.  Throws kifmm::Error.
+void evaluate_forest_noalloc(EvalState& st, const HostOps& hops, OpsCache& oc, const void* charges,
+                             void* potentials, int n_rhs, bool io_fp64, kifmm_precision prec, void* stream);
 
 // Host-memory convenience: copies charges in, evaluates in FP32 with FP64
 // input/output on the default stream, copies potentials out, synchronously.

@@ -15,6 +15,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 #include <cstring>
@@ -2263,6 +2265,111 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
 }
 
 int64_t graph_captures() { return g_graph_captures.load(); }
+
+// ------------------------------------------------------------------------
+// allocation-free evaluation
+// ------------------------------------------------------------------------
+
+// The work buffers of kifmm_evaluate_noalloc, carved from this array on every
+// call.  Every device that runs the library holds its own copy until the
+// process ends; host code uses the per-device address from
+// hipGetSymbolAddress, never the array's name.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_addr;
+
+// Device address of `scratch` on the current device (looked up once per device).
+static unsigned char* scratch_address(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it != g_scratch_addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    raise(KIFMM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_addr[dev] = static_cast<unsigned char*>(p);
+  return static_cast<unsigned char*>(p);
+}
+
+void evaluate_forest_noalloc(EvalState& st, const HostOps& hops, OpsCache& oc, const void* charges,
+                             void* potentials, int n_rhs, bool io_fp64, kifmm_precision prec, void* stream) {
+  const int dev = current_device();
+  if (!st.forest || st.device != dev)
+    raise(KIFMM_EINVAL, "evaluate_noalloc: the tree has no device state on this device (run kifmm_evaluate once)");
+  if (g_prof.on) raise(KIFMM_EINVAL, "evaluate_noalloc: phase profiling is on (it creates events)");
+  const bool fp64 = prec == KIFMM_FP64 || prec == KIFMM_FP64_M2L_FP32 || prec == KIFMM_FP64_M2L_F16X3;
+  OpsNeed need;
+  need.m2l32 = prec == KIFMM_FP32 || prec == KIFMM_FP64_M2L_FP32;
+  need.bf16 = prec == KIFMM_M2L_BF16X3 || prec == KIFMM_M2L_BF16X5;
+  need.f16 = prec == KIFMM_M2L_F16X3 || prec == KIFMM_FP64_M2L_F16X3;
+  need.check_form = (need.m2l32 || need.f16) && hops.p >= g_m2l_check_min_p && hops.kernel == 0;
+  auto it = oc.per_device.find(dev);
+  DevOps* O = it == oc.per_device.end() ? nullptr : it->second;
+  const bool ready =
+      O && (fp64 ? (O->m2m64 && O->l2l64) : (O->m2m32 && O->l2l32)) && (prec != KIFMM_FP64 || O->m2l64) &&
+      (!need.m2l32 || (need.check_form ? O->m2lc32 : O->m2l32) != nullptr) &&
+      (!need.f16 || (need.check_form ? O->m2lc_h : O->m2l_h) != nullptr) && (!need.bf16 || O->m2l_b);
+  if (!ready)
+    raise(KIFMM_EINVAL,
+          "evaluate_noalloc: the operator tables of this precision are not on this device (run kifmm_evaluate once)");
+  DevForest& F = *st.forest;
+  if (F.n != hops.n) raise(KIFMM_EINVAL, "evaluate_noalloc: operator order differs from the cached forest");
+  if ((hops.kernel != 0) != st.host->per_level)
+    raise(KIFMM_EINVAL, "evaluate_noalloc: the cached plans were built for another kernel");
+
+  // layout: the regions that must start at zero first, then the rest
+  const size_t es = fp64 ? 8 : 4;
+  const size_t cols = size_t(F.nbox + 1) * n_rhs * F.ld;
+  auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+  DevWork W;
+  W.n_rhs = n_rhs;
+  W.fp64 = fp64;
+  W.col_bytes = cols * es;
+  W.split_bytes = (need.bf16 || need.f16) ? cols * 3 * 2 : 0;
+  W.pair_bytes = size_t(F.n_pairs) * n_rhs * F.ld * es;
+  size_t off = 0;
+  size_t at[8];
+  const size_t sizes[8] = {W.col_bytes, W.col_bytes, W.col_bytes, W.col_bytes, W.split_bytes, 256,
+                           size_t(n_rhs) * F.nsrc * es, size_t(n_rhs) * F.ntgt * 8};
+  for (int k = 0; k < 8; ++k) {
+    at[k] = off;
+    off += up256(sizes[k]);
+  }
+  const size_t zero_bytes = at[6];  // four column buffers, split operand, absmax word
+  const size_t pairs_at = off;
+  off += up256(W.pair_bytes);
+  if (off > kNoAllocScratchBytes)
+    raise(KIFMM_EUNSUPPORTED, "evaluate_noalloc: this evaluation needs " + std::to_string(off >> 20) +
+                                  " MiB of work buffers; the allocation-free entry point holds " +
+                                  std::to_string(kNoAllocScratchBytes >> 20) + " MiB");
+  unsigned char* base = scratch_address(dev);
+  W.up_chk = base + at[0];
+  W.up_eq = base + at[1];
+  W.dn_chk = base + at[2];
+  W.dn_eq = base + at[3];
+  W.split = W.split_bytes ? base + at[4] : nullptr;
+  W.absmax = reinterpret_cast<unsigned*>(base + at[5]);
+  W.qs = base + at[6];
+  W.pot = reinterpret_cast<double*>(base + at[7]);
+  W.pairs = W.pair_bytes ? base + pairs_at : nullptr;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the array keeps the previous call's values: padding rows and the zero
+  // box's columns must read zero (a fill kernel, not a memset, so that a
+  // caller can capture the call into a graph)
+  hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, s, reinterpret_cast<uint4*>(base),
+                     int64_t(zero_bytes / 16));
+  LAUNCHCHECK("zero_kernel");
+  const void* q[1] = {charges};
+  void* o[1] = {potentials};
+  if (fp64) {
+    if (io_fp64) pipeline<double, double>(F, *O, W, q, o, n_rhs, prec, need.check_form, false, s);
+    else pipeline<double, float>(F, *O, W, q, o, n_rhs, prec, need.check_form, false, s);
+  } else {
+    if (io_fp64) pipeline<float, double>(F, *O, W, q, o, n_rhs, prec, need.check_form, false, s);
+    else pipeline<float, float>(F, *O, W, q, o, n_rhs, prec, need.check_form, false, s);
+  }
+}
 
 void debug_buffer(EvalState& st, int which, bool fp64, int n_rhs, double* out, int64_t n_out) {
   if (!st.forest) raise(KIFMM_EINVAL, "debug_buffer: no evaluation has run on this tree");

@@ -46,7 +46,8 @@ EXPORTED = [
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
     "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_precompute_operators_screened",
     "kifmm_ops_save", "kifmm_ops_load",
-    "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
+    "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_noalloc",
+    "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
     "kifmm_get_phase_times", "kifmm_graph_captures", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
@@ -80,6 +81,7 @@ def lib():
     L.kifmm_ops_levels.argtypes = [P]
     L.kifmm_ops_levels.restype = I32
     L.kifmm_evaluate.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
+    L.kifmm_evaluate_noalloc.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
     L.kifmm_evaluate_gradient.argtypes = [P, P, P, I32, P, I32, C.c_int, P]
     L.kifmm_evaluate_batch.argtypes = [I32, C.POINTER(P), P, C.POINTER(P), C.POINTER(P), I32,
                                        C.c_int, P]
@@ -305,6 +307,27 @@ def evaluate(tree: Tree, ops: Operators, charges, precision="fp32", out=None, st
                                 C.c_void_p(out.data_ptr()), 1 if q.dtype == torch.float64 else 0,
                                 prec, _stream_ptr(stream)))
     return out.reshape(inf.n_tgt) if one else out.reshape(n_rhs, inf.n_tgt)
+
+
+def evaluate_noalloc(tree: Tree, ops: Operators, charges, out, precision="fp32", stream=None):
+    """kifmm_evaluate_noalloc: like evaluate, with every work buffer taken from
+    the library's fixed device array; allocates nothing, so `charges`
+    ([n_rhs][n_src]) and `out` ([n_rhs][n_tgt], same dtype) must be given
+    contiguous.  Needs one evaluate() of the same tree, operators, n_rhs and
+    precision on this device first."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    if not charges.is_cuda or not charges.is_contiguous():
+        raise ValueError("charges must be a contiguous CUDA (HIP) tensor")
+    inf = tree.info()
+    n_rhs = charges.numel() // max(inf.n_src, 1)
+    if n_rhs * inf.n_src != charges.numel():
+        raise ValueError(f"charges hold {charges.numel()} values, not a multiple of {inf.n_src} sources")
+    _check_out(out, n_rhs * inf.n_tgt, charges)
+    import torch
+    _check(lib().kifmm_evaluate_noalloc(tree.handle, ops.handle, C.c_void_p(charges.data_ptr()), n_rhs,
+                                        C.c_void_p(out.data_ptr()), 1 if charges.dtype == torch.float64 else 0,
+                                        prec, _stream_ptr(stream)))
+    return out
 
 
 def _check_out(out, numel, q):
