@@ -103,6 +103,23 @@ kifmm_status kifmm_build_tree(const double* src_xyz, int64_t n_src,
                               const double* tgt_xyz, int64_t n_tgt,
                               const kifmm_tree_params* params, kifmm_tree** out);
 
+/* The same tree built on the current GPU (section "Data-oriented design of
+ * PyExaFMM": linear octree of Morton-sorted points; lists of section
+ * "Computational structure of FMM operators"): root, keys, stable sort,
+ * refinement, 2:1 balance, numbering and the U, V, W, X lists run as
+ * kernels, and the result is equal, integer for integer (keys, point order,
+ * boxes, lists), to kifmm_build_tree on the same coordinates; the host copy
+ * is filled from the device.  src_xyz [n_src][3], tgt_xyz [n_tgt][3]: DEVICE
+ * FP64 (tgt_xyz == src_xyz with n_tgt == n_src: the same points, as in
+ * kifmm_build_tree).  Work is ordered on hip_stream (NULL: the default
+ * stream), which is synchronised before return.  Errors as
+ * kifmm_build_tree, plus EINVAL for host pointers; EUNSUPPORTED past the
+ * device scan limit (about 8M boxes on one level). */
+kifmm_status kifmm_build_tree_device(const double* src_xyz, int64_t n_src,
+                                     const double* tgt_xyz, int64_t n_tgt,
+                                     const kifmm_tree_params* params, void* hip_stream,
+                                     kifmm_tree** out);
+
 kifmm_status kifmm_tree_get_info(const kifmm_tree* tree, kifmm_tree_info* info);
 
 /* Copy the box table out (for inspection and tests).  Boxes are numbered

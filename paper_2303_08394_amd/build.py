@@ -17,7 +17,7 @@ OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkifmm.so")
 
 HOST_SOURCES = ["host_tree.cpp", "precompute.cpp", "forest.cpp", "api.cpp"]
-HIP_SOURCES = ["evaluate.hip", "tree_update.hip", "precompute_device.hip"]
+HIP_SOURCES = ["evaluate.hip", "tree_update.hip", "tree_build.hip", "precompute_device.hip"]
 ARCH = "gfx950"
 
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-Wall",

@@ -151,6 +151,18 @@ kifmm_status kifmm_build_tree(const double* src_xyz, int64_t n_src, const double
   });
 }
 
+kifmm_status kifmm_build_tree_device(const double* src_xyz, int64_t n_src, const double* tgt_xyz,
+                                     int64_t n_tgt, const kifmm_tree_params* params, void* hip_stream,
+                                     kifmm_tree** out) {
+  if (!out) return fail(KIFMM_EINVAL, "build_tree_device: null output handle");
+  if (!params) return fail(KIFMM_EINVAL, "build_tree_device: null params");
+  return guard([&] {
+    auto t = std::make_unique<kifmm_tree>();
+    t->host.reset(build_tree_device(src_xyz, n_src, tgt_xyz, n_tgt, *params, hip_stream));
+    *out = t.release();
+  });
+}
+
 kifmm_status kifmm_tree_get_info(const kifmm_tree* tree, kifmm_tree_info* info) {
   if (!tree || !info) return fail(KIFMM_EINVAL, "tree_get_info: null argument");
   const HostTree& T = *tree->host;

@@ -100,6 +100,13 @@ bool pending_stale(const PendingPoints* p);
 int pending_device(const PendingPoints* p);
 void pending_free(PendingPoints* p);
 
+// The tree of build_host_tree built on the current device from DEVICE
+// coordinates src [nsrc][3] and tgt [ntgt][3] (tgt == src: the same array):
+// equal to the host build integer for integer; synchronises the stream.
+// Throws Error (EINVAL as build_host_tree, or for host pointers).
+HostTree* build_tree_device(const double* src, int64_t nsrc, const double* tgt, int64_t ntgt,
+                            const kifmm_tree_params& prm, void* stream);
+
 // smallest order at which FP32-bulk modes evaluate L2P/M2P terms in FP64
 void set_far_fp64_min_p(int p);
 // smallest order at which FP32/FP16 M2L runs on check potentials with the

@@ -317,9 +317,7 @@ static void build_lists(HostTree& T, const std::unordered_map<uint64_t, int32_t>
   }
 }
 
-HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, int64_t ntgt,
-                          const kifmm_tree_params& prm) {
-  if (!src || !tgt) raise(KIFMM_EINVAL, "build_tree: null point array");
+void validate_tree_params(int64_t nsrc, int64_t ntgt, const kifmm_tree_params& prm) {
   if (nsrc < 1 || ntgt < 1) raise(KIFMM_EINVAL, "build_tree: n_src and n_tgt must be >= 1");
   if (nsrc > (int64_t(1) << 31) - 1 || ntgt > (int64_t(1) << 31) - 1)
     raise(KIFMM_EINVAL, "build_tree: at most 2^31-1 points");
@@ -332,6 +330,32 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
   }
   if (prm.root_halfwidth < 0 || !std::isfinite(prm.root_halfwidth))
     raise(KIFMM_EINVAL, "build_tree: root_halfwidth must be finite and >= 0");
+  if (prm.root_halfwidth > 0)
+    for (int d = 0; d < 3; ++d)
+      if (!std::isfinite(prm.root_center[d])) raise(KIFMM_EINVAL, "build_tree: non-finite root centre");
+}
+
+void set_tree_root(HostTree& T, const kifmm_tree_params& prm, const double mn[3], const double mx[3]) {
+  if (prm.root_halfwidth > 0) {
+    for (int d = 0; d < 3; ++d) T.c0[d] = prm.root_center[d];
+    T.r0 = prm.root_halfwidth;
+  } else {
+    double ext = 0;
+    for (int d = 0; d < 3; ++d) {
+      T.c0[d] = 0.5 * (mn[d] + mx[d]);
+      ext = std::max(ext, mx[d] - mn[d]);
+    }
+    double r = 0.5 * ext * (1.0 + std::ldexp(1.0, -20));
+    T.r0 = r > 0 ? r : 0.5;
+  }
+  for (int d = 0; d < 3; ++d) T.lo[d] = T.c0[d] - T.r0;
+  T.key_level = prm.uniform_depth >= 0 ? prm.uniform_depth : prm.max_depth;
+}
+
+HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, int64_t ntgt,
+                          const kifmm_tree_params& prm) {
+  if (!src || !tgt) raise(KIFMM_EINVAL, "build_tree: null point array");
+  validate_tree_params(nsrc, ntgt, prm);
   for (int64_t i = 0; i < 3 * nsrc; ++i)
     if (!std::isfinite(src[i])) raise(KIFMM_EINVAL, "build_tree: non-finite source coordinate");
   for (int64_t i = 0; i < 3 * ntgt; ++i)
@@ -342,27 +366,9 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
   try {
     T.nsrc = nsrc;
     T.ntgt = ntgt;
-    if (prm.root_halfwidth > 0) {
-      for (int d = 0; d < 3; ++d) {
-        if (!std::isfinite(prm.root_center[d])) raise(KIFMM_EINVAL, "build_tree: non-finite root centre");
-        T.c0[d] = prm.root_center[d];
-      }
-      T.r0 = prm.root_halfwidth;
-      // a point outside the given root cube would be clamped into a boundary
-      // leaf, beyond that leaf's equivalent surface: refused
-      auto inside = [&](const double* x, int64_t n) {
-        for (int64_t i = 0; i < n; ++i)
-          for (int d = 0; d < 3; ++d) {
-            const double t = (x[3 * i + d] - (T.c0[d] - T.r0)) / (2.0 * T.r0);
-            if (!(t >= 0.0 && t <= 1.0)) return false;
-          }
-        return true;
-      };
-      if (!inside(src, nsrc) || !inside(tgt, ntgt))
-        raise(KIFMM_EINVAL, "build_tree: a point lies outside the given root box");
-    } else {
-      double mn[3], mx[3];
-      for (int d = 0; d < 3; ++d) mn[d] = mx[d] = src[d];
+    double mn[3], mx[3];
+    for (int d = 0; d < 3; ++d) mn[d] = mx[d] = src[d];
+    if (prm.root_halfwidth <= 0) {
       auto upd = [&](const double* x, int64_t n) {
         for (int64_t i = 0; i < n; ++i)
           for (int d = 0; d < 3; ++d) {
@@ -372,16 +378,22 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
       };
       upd(src, nsrc);
       upd(tgt, ntgt);
-      double ext = 0;
-      for (int d = 0; d < 3; ++d) {
-        T.c0[d] = 0.5 * (mn[d] + mx[d]);
-        ext = std::max(ext, mx[d] - mn[d]);
-      }
-      double r = 0.5 * ext * (1.0 + std::ldexp(1.0, -20));
-      T.r0 = r > 0 ? r : 0.5;
     }
-    for (int d = 0; d < 3; ++d) T.lo[d] = T.c0[d] - T.r0;
-    T.key_level = prm.uniform_depth >= 0 ? prm.uniform_depth : prm.max_depth;
+    set_tree_root(T, prm, mn, mx);
+    if (prm.root_halfwidth > 0) {
+      // a point outside the given root cube would be clamped into a boundary
+      // leaf, beyond that leaf's equivalent surface: refused
+      auto inside = [&](const double* x, int64_t n) {
+        for (int64_t i = 0; i < n; ++i)
+          for (int d = 0; d < 3; ++d) {
+            const double t = (x[3 * i + d] - T.lo[d]) / (2.0 * T.r0);
+            if (!(t >= 0.0 && t <= 1.0)) return false;
+          }
+        return true;
+      };
+      if (!inside(src, nsrc) || !inside(tgt, ntgt))
+        raise(KIFMM_EINVAL, "build_tree: a point lies outside the given root box");
+    }
     T.tgt_is_src = tgt == src && ntgt == nsrc;
 
     sort_points(src, nsrc, T.lo, T.r0, T.key_level, T.sperm, T.sxyz, T.skey);

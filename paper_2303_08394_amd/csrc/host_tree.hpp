@@ -44,6 +44,12 @@ struct HostTree {
   int64_t ntgt_of(int32_t b) const { return tend[b] - tbeg[b]; }
 };
 
+// Argument checks shared by the host and the device build (EINVAL).
+void validate_tree_params(int64_t nsrc, int64_t ntgt, const kifmm_tree_params& prm);
+// Root box (given, or the bounding cube of the points' per-axis minima mn and
+// maxima mx), lower corner and key level of T.
+void set_tree_root(HostTree& T, const kifmm_tree_params& prm, const double mn[3], const double mx[3]);
+
 // Builds the tree and its lists.  Throws kifmm::Error on bad input.
 HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, int64_t ntgt,
                           const kifmm_tree_params& prm);

@@ -26,183 +26,10 @@
 #include "device.hpp"
 #include "hip_check.hpp"
 #include "host_tree.hpp"
+#include "keys_sort.hpp"
 
 namespace kifmm {
 namespace {
-
-constexpr int kThreads = 256;   // = the 256 digits of a pass
-constexpr int kItems = 16;      // keys per thread and block tile
-constexpr int kTile = kThreads * kItems;
-typedef unsigned long long u64;
-
-__device__ inline u64 spread3(u64 v) {  // bit k of v -> bit 3k (k < 21)
-  v &= 0x1fffffull;
-  v = (v | (v << 32)) & 0x1f00000000ffffull;
-  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
-  v = (v | (v << 8)) & 0x100f00f00f00f00full;
-  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
-  v = (v | (v << 2)) & 0x1249249249249249ull;
-  return v;
-}
-__device__ inline u64 morton3(u64 x, u64 y, u64 z) { return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z); }
-
-struct Frame {
-  double lo[3];
-  double r0;  // root half-width
-  int L;      // key level
-};
-
-// A point outside the closed root cube (t outside [0, 1] on some axis, or
-// not a number) is counted in *outside: the update is then refused, as the
-// clamp would put it in a boundary leaf beyond that leaf's equivalent surface.
-__global__ void key_kernel(const double* __restrict__ xyz, int64_t n, Frame f, u64* __restrict__ keys,
-                           int32_t* __restrict__ idx, unsigned long long* __restrict__ outside) {
-#pragma clang fp contract(off)
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double cells = double(int64_t(1) << f.L), maxi = cells - 1.0;
-  u64 ix[3];
-  bool inside = true;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double t = (xyz[3 * i + d] - f.lo[d]) / (2.0 * f.r0);
-    inside = inside && t >= 0.0 && t <= 1.0;
-    double c = floor(t * cells);
-    if (!(c >= 0.0)) c = 0.0;
-    if (c > maxi) c = maxi;
-    ix[d] = u64(c);
-  }
-  keys[i] = morton3(ix[0], ix[1], ix[2]);
-  idx[i] = int32_t(i);
-  if (!inside) atomicAdd(outside, 1ull);
-}
-
-// Digit counts of each block's tile, stored digit-major: hist[digit][block].
-__global__ void radix_hist_kernel(const u64* __restrict__ keys, int64_t n, int shift,
-                                  uint32_t* __restrict__ hist, int nblk) {
-  __shared__ uint32_t h[kThreads];
-  const int tid = threadIdx.x;
-  h[tid] = 0;
-  __syncthreads();
-  const int64_t base = int64_t(blockIdx.x) * kTile;
-  for (int k = 0; k < kItems; ++k) {
-    const int64_t i = base + k * kThreads + tid;
-    if (i < n) atomicAdd(&h[unsigned(keys[i] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[int64_t(tid) * nblk + blockIdx.x] = h[tid];
-}
-
-// Exclusive prefix sum of a[0..m) in place, in three launches: each block
-// of 1024 threads scans its chunk (wave shuffles, then the waves' totals) and
-// records the chunk's total; one block scans those totals; every element
-// then adds its chunk's offset.
-__global__ __launch_bounds__(1024) void scan_chunks_kernel(uint32_t* a, int64_t m, uint32_t* totals) {
-  __shared__ uint32_t wsum[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t i = int64_t(blockIdx.x) * 1024 + tid;
-  const uint32_t v = i < m ? a[i] : 0u;
-  uint32_t s = v;  // inclusive scan within the wave
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t t = __shfl_up(s, off, 64);
-    if (lane >= off) s += t;
-  }
-  if (lane == 63) wsum[w] = s;
-  __syncthreads();
-  uint32_t before = 0;
-  for (int k = 0; k < w; ++k) before += wsum[k];
-  if (i < m) a[i] = before + s - v;
-  if (tid == 1023) totals[blockIdx.x] = before + s;
-}
-
-__global__ __launch_bounds__(1024) void scan_totals_kernel(uint32_t* totals, int n) {
-  // n <= 1024 * 64: each thread scans a run of consecutive totals
-  __shared__ uint32_t part[1024];
-  const int tid = threadIdx.x, per = (n + 1023) / 1024;
-  const int b = tid * per, e = min(n, b + per);
-  uint32_t sum = 0;
-  for (int k = b; k < e; ++k) sum += totals[k];
-  part[tid] = sum;
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int k = 0; k < 1024; ++k) {
-      const uint32_t x = part[k];
-      part[k] = run;
-      run += x;
-    }
-  }
-  __syncthreads();
-  uint32_t run = part[tid];
-  for (int k = b; k < e; ++k) {
-    const uint32_t x = totals[k];
-    totals[k] = run;
-    run += x;
-  }
-}
-
-__global__ void scan_add_kernel(uint32_t* a, int64_t m, const uint32_t* totals) {
-  const int64_t i = int64_t(blockIdx.x) * 1024 + threadIdx.x;
-  if (i < m) a[i] += totals[blockIdx.x];
-}
-
-// Stable scatter of one pass.  Each block walks its tile in chunks of 256
-// keys (one per thread, in order); a key's place is its digit's running base
-// for the block + the counts of its digit in lower waves of the chunk + its
-// rank among the lanes of its wave with the same digit (found with ballots).
-__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
-    const u64* __restrict__ kin, const int32_t* __restrict__ vin, int64_t n, int shift,
-    const uint32_t* __restrict__ hist, int nblk, u64* __restrict__ kout, int32_t* __restrict__ vout) {
-  constexpr int NW = kThreads / 64;
-  __shared__ uint32_t base[kThreads];
-  __shared__ uint32_t wcnt[NW][kThreads];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  base[tid] = hist[int64_t(tid) * nblk + blockIdx.x];
-  const int64_t t0 = int64_t(blockIdx.x) * kTile;
-  for (int k = 0; k < kItems; ++k) {
-#pragma unroll
-    for (int q = 0; q < NW; ++q) wcnt[q][tid] = 0;
-    __syncthreads();
-    const int64_t i = t0 + k * kThreads + tid;
-    const bool valid = i < n;  // invalid lanes only follow valid ones
-    const u64 key = valid ? kin[i] : ~0ull;
-    const int32_t val = valid ? vin[i] : 0;
-    const uint32_t d = unsigned(key >> shift) & 255u;
-    unsigned long long peers = ~0ull;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const unsigned long long m = __ballot(bit);
-      peers &= bit ? m : ~m;
-    }
-    const unsigned long long lower = peers & ((1ull << lane) - 1ull);
-    if (lower == 0ull) wcnt[w][d] = uint32_t(__popcll(peers));
-    __syncthreads();
-    uint32_t pos = base[d] + uint32_t(__popcll(lower));
-    for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-    if (valid) {
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    uint32_t add = 0;
-#pragma unroll
-    for (int q = 0; q < NW; ++q) add += wcnt[q][tid];
-    base[tid] += add;
-    __syncthreads();
-  }
-}
-
-// Sorted raw coordinates of every sorted point.
-__global__ void gather_sorted_kernel(const double* __restrict__ xyz, const int32_t* __restrict__ perm, int64_t n,
-                                     double* __restrict__ sorted_xyz) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t j = perm[i];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) sorted_xyz[3 * i + d] = xyz[3 * j + d];
-}
 
 // Leaf-frame coordinates (x - c) / r of the points of each leaf (one block
 // per leaf box; c and r from its anchor and level, as the host computes them).
@@ -219,16 +46,6 @@ __global__ void leaf_frame_kernel(const int32_t* __restrict__ leaves, const int3
   for (int i = rg.x + threadIdx.x; i < rg.y; i += blockDim.x)
     rel[i] = make_double4((sorted_xyz[3 * i] - c[0]) / r, (sorted_xyz[3 * i + 1] - c[1]) / r,
                           (sorted_xyz[3 * i + 2] - c[2]) / r, 0.0);
-}
-
-__device__ inline int64_t lower_bound_u64(const u64* a, int64_t n, u64 v) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] < v) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
 }
 
 // New point range of every box; flags a leaf whose emptiness changed (occ:
@@ -253,13 +70,6 @@ __global__ void ranges_kernel(const int32_t* __restrict__ anchor, const int32_t*
   }
 }
 
-template <class T>
-T* dalloc(std::vector<void*>& owned, size_t count) {
-  void* p = nullptr;
-  HIPCHECK(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
-  owned.push_back(p);
-  return static_cast<T*>(p);
-}
 
 }  // namespace
 
@@ -353,29 +163,9 @@ static void sort_set(PendingPoints& P, const HostTree& T, const double* xyz, int
   const unsigned grid = unsigned((n + 255) / 256);
   hipLaunchKernelGGL(key_kernel, dim3(grid), dim3(256), 0, s, xyz, n, f, P.k0, P.v0, P.stat + 3);
   LAUNCHCHECK("key_kernel");
-  const int nblk = int((n + kTile - 1) / kTile);
-  const int64_t m = int64_t(kThreads) * nblk;  // scanned entries
-  const int nchunk = int((m + 1023) / 1024);
-  const int passes = (3 * T.key_level + 7) / 8;
-  u64 *kin = P.k0, *kout = S.keys;
-  int32_t *vin = P.v0, *vout = S.perm;
-  for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL(radix_hist_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, n, 8 * p, P.hist, nblk);
-    LAUNCHCHECK("radix_hist_kernel");
-    hipLaunchKernelGGL(scan_chunks_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, P.hist, m, P.totals);
-    LAUNCHCHECK("scan_chunks_kernel");
-    hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(1024), 0, s, P.totals, nchunk);
-    LAUNCHCHECK("scan_totals_kernel");
-    hipLaunchKernelGGL(scan_add_kernel, dim3(unsigned(nchunk)), dim3(1024), 0, s, P.hist, m, P.totals);
-    LAUNCHCHECK("scan_add_kernel");
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3(nblk), dim3(kThreads), 0, s, kin, vin, n, 8 * p, P.hist,
-                       nblk, kout, vout);
-    LAUNCHCHECK("radix_scatter_kernel");
-    std::swap(kin, kout);
-    std::swap(vin, vout);
-  }
-  // the sorted keys and order are in (kin, vin); the set keeps its own
-  if (kin == P.k0) {
+  const bool in_set = radix_sort_pairs(P.k0, P.v0, S.keys, S.perm, n, 3 * T.key_level, P.hist, P.totals, s);
+  // the set keeps its own sorted keys and order
+  if (!in_set) {
     HIPCHECK(hipMemcpyAsync(S.keys, P.k0, size_t(n) * 8, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemcpyAsync(S.perm, P.v0, size_t(n) * 4, hipMemcpyDeviceToDevice, s));
   }

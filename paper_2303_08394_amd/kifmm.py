@@ -42,7 +42,7 @@ class TreeInfo(C.Structure):
 
 _lib = None
 EXPORTED = [
-    "kifmm_build_tree", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
+    "kifmm_build_tree", "kifmm_build_tree_device", "kifmm_tree_get_info", "kifmm_tree_export_boxes",
     "kifmm_tree_export_list", "kifmm_tree_export_perm", "kifmm_tree_update_points",
     "kifmm_precompute_operators", "kifmm_precompute_operators_ex", "kifmm_precompute_operators_screened",
     "kifmm_ops_save", "kifmm_ops_load",
@@ -64,6 +64,7 @@ def lib():
     L = C.CDLL(LIB_PATH)
     P, D, I32, I64 = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64
     L.kifmm_build_tree.argtypes = [D, I64, D, I64, C.POINTER(TreeParams), C.POINTER(P)]
+    L.kifmm_build_tree_device.argtypes = [P, I64, P, I64, C.POINTER(TreeParams), P, C.POINTER(P)]
     L.kifmm_tree_get_info.argtypes = [P, C.POINTER(TreeInfo)]
     L.kifmm_tree_export_boxes.argtypes = [P, P, P, P, P, P, P]
     L.kifmm_tree_export_list.argtypes = [P, I32, P, P]
@@ -123,26 +124,51 @@ def _vptr(a):
     return C.c_void_p(a.ctypes.data) if a is not None else None
 
 
+def _params(uniform_depth, ncrit, max_depth, balance, center, halfwidth) -> TreeParams:
+    prm = TreeParams()
+    prm.uniform_depth = uniform_depth
+    prm.ncrit = ncrit
+    prm.max_depth = max_depth
+    prm.balance = 1 if balance else 0
+    if halfwidth and halfwidth > 0:
+        prm.root_center[:] = [float(v) for v in center]
+        prm.root_halfwidth = float(halfwidth)
+    return prm
+
+
 class Tree:
     """Octree + interaction lists built by the library (host)."""
 
     def __init__(self, src, tgt=None, *, uniform_depth: int = -1, ncrit: int = 64,
-                 max_depth: int = 12, balance: bool = True, center=None, halfwidth: float = 0.0):
+                 max_depth: int = 12, balance: bool = True, center=None, halfwidth: float = 0.0,
+                 _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            return
         L = lib()
-        self.src = np.ascontiguousarray(src, dtype=np.float64)
-        self.tgt = self.src if tgt is None else np.ascontiguousarray(tgt, dtype=np.float64)
-        prm = TreeParams()
-        prm.uniform_depth = uniform_depth
-        prm.ncrit = ncrit
-        prm.max_depth = max_depth
-        prm.balance = 1 if balance else 0
-        if halfwidth and halfwidth > 0:
-            prm.root_center[:] = [float(v) for v in center]
-            prm.root_halfwidth = float(halfwidth)
+        src = np.ascontiguousarray(src, dtype=np.float64)
+        tgt = src if tgt is None else np.ascontiguousarray(tgt, dtype=np.float64)
+        prm = _params(uniform_depth, ncrit, max_depth, balance, center, halfwidth)
         h = C.c_void_p()
-        _check(L.kifmm_build_tree(_dptr(self.src), len(self.src), _dptr(self.tgt), len(self.tgt),
-                                  C.byref(prm), C.byref(h)))
+        _check(L.kifmm_build_tree(_dptr(src), len(src), _dptr(tgt), len(tgt), C.byref(prm), C.byref(h)))
         self._h = h
+
+    @classmethod
+    def on_device(cls, src, tgt=None, *, stream=None, uniform_depth: int = -1, ncrit: int = 64,
+                  max_depth: int = 12, balance: bool = True, center=None, halfwidth: float = 0.0):
+        """The same tree built on the GPU (kifmm_build_tree_device) from
+        contiguous float64 CUDA tensors [n][3]; tgt None: the sources."""
+        import torch
+        for a in (src, tgt):
+            if a is not None and (not a.is_cuda or a.dtype != torch.float64 or a.dim() != 2
+                                  or a.shape[1] != 3 or not a.is_contiguous()):
+                raise ValueError("on_device: contiguous float64 CUDA tensors of shape [n, 3]")
+        t = src if tgt is None else tgt
+        prm = _params(uniform_depth, ncrit, max_depth, balance, center, halfwidth)
+        h = C.c_void_p()
+        _check(lib().kifmm_build_tree_device(C.c_void_p(src.data_ptr()), src.shape[0], C.c_void_p(t.data_ptr()),
+                                             t.shape[0], C.byref(prm), _stream_ptr(stream), C.byref(h)))
+        return cls(None, _handle=h)
 
     @property
     def handle(self):
