@@ -309,6 +309,14 @@ int32_t kifmm_n_phases(void);
  * replays it otherwise).  An operator set made after another was destroyed
  * never replays the other's graph, even at the same address.  Never fails. */
 int64_t kifmm_graph_captures(void);
+
+/* Test hook for the out-of-memory paths: after `after` more allocation
+ * points of the library succeed (host tree, plan and operator builds, every
+ * device allocation), the next one fails as an allocation would, with
+ * KIFMM_ENOMEM, and the hook disarms itself; after < 0 disarms it.  A call
+ * that fails this way leaves its handles and cached state as they were
+ * before the call.  Process-wide; not for production use. */
+void kifmm_debug_fail_allocations(int64_t after);
 const char* kifmm_phase_name(int32_t i);
 kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches);
 

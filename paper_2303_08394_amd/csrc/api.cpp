@@ -348,10 +348,12 @@ static kifmm_status evaluate_impl(const kifmm_tree* tree, const kifmm_ops* ops, 
       rebuild = true;
     }
     if (rebuild) {
-      t->state.reset(new EvalState());
+      // the new state replaces the old one only once its plans exist
+      std::unique_ptr<EvalState> st(new EvalState());
       const HostTree* one = t->host.get();
-      t->state->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0,
-                                        pair_fill(n), max_pairs(n, n_rhs), per_level));
+      st->host.reset(build_forest(&one, 1, *ops->host, TB, TBm, g_m2l_split.load() != 0, pair_fill(n),
+                                  max_pairs(n, n_rhs), per_level));
+      t->state = std::move(st);
       t->state_n = ops->host->n;
     }
     check_operand_limits(t->state->host->nbox, n_rhs, n);
@@ -568,6 +570,8 @@ kifmm_status kifmm_set_profiling(int32_t enable) {
   return KIFMM_OK;
 }
 int64_t kifmm_graph_captures(void) { return graph_captures(); }
+
+void kifmm_debug_fail_allocations(int64_t after) { alloc_fail_counter() = after < 0 ? -1 : after; }
 int32_t kifmm_n_phases(void) { return n_phases(); }
 const char* kifmm_phase_name(int32_t i) { return phase_name(i); }
 kifmm_status kifmm_get_phase_times(double* ms, int64_t* launches) {

@@ -2,6 +2,7 @@
 // a small parallel-for over std::thread.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -23,6 +24,25 @@ struct Error {
 };
 
 [[noreturn]] inline void raise(kifmm_status st, const std::string& msg) { throw Error{st, msg}; }
+
+// Allocation-failure injection (kifmm_debug_fail_allocations): every host
+// build step and device allocation of the library calls alloc_hook first;
+// the call that finds the counter at 0 fails with ENOMEM and disarms it
+// (-1).  One counter per process, shared by every source file.
+inline std::atomic<int64_t>& alloc_fail_counter() {
+  static std::atomic<int64_t> c{-1};
+  return c;
+}
+inline void alloc_hook(const char* what) {
+  auto& c = alloc_fail_counter();
+  int64_t v = c.load();
+  while (v >= 0) {
+    if (c.compare_exchange_weak(v, v - 1)) {
+      if (v == 0) raise(KIFMM_ENOMEM, std::string(what) + ": allocation failure injected by the test hook");
+      return;
+    }
+  }
+}
 
 inline int hw_threads() {
   unsigned n = std::thread::hardware_concurrency();

@@ -168,6 +168,7 @@ int current_device() {
 template <class T>
 static T* dev_alloc(std::vector<void*>& allocs, size_t count) {
   if (count == 0) count = 1;
+  alloc_hook("hipMalloc");
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, count * sizeof(T));
   if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -352,9 +353,13 @@ struct OpsNeed {
 };
 
 static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const OpsNeed& need) {
-  DevOps*& O = oc.per_device[dev];
+  DevOps* O = nullptr;
+  if (auto it = oc.per_device.find(dev); it != oc.per_device.end()) O = it->second;
   if (!O) {
-    O = new DevOps();
+    // the base tables first, entered into the cache only when complete; the
+    // optional tables below are each set only once uploaded
+    std::unique_ptr<DevOps> Op(new DevOps());
+    O = Op.get();
     O->n = H.n;
     O->p = H.p;
     O->ld = round32(H.n);
@@ -366,6 +371,7 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
     for (int i = 0; i < H.n; ++i)
       for (int d = 0; d < 3; ++d) s4[4 * i + d] = H.surf[3 * i + d];
     O->surf = dev_upload<double4>(O->allocs, s4);
+    oc.per_device[dev] = Op.release();
   }
   if (need.bulk64 && !O->m2m64)
     O->m2m64 = dev_upload<double>(O->allocs, pad_table<double>(H.m2m, 8 * H.levels, H.n, O->ld));
@@ -403,9 +409,13 @@ static DevOps* ops_for_device(OpsCache& oc, const HostOps& H, int dev, const Ops
 
 static DevWork* work_for(DevForest& F, bool fp64, int n_rhs, bool grad = false) {
   // (buffers of gradient evaluations are kept apart: 4 values per target)
-  DevWork*& W = F.work[{(fp64 ? 1 : 0) | (grad ? 2 : 0), n_rhs}];
-  if (W) return W;
-  W = new DevWork();
+  const std::pair<int, int> key{(fp64 ? 1 : 0) | (grad ? 2 : 0), n_rhs};
+  auto found = F.work.find(key);
+  if (found != F.work.end()) return found->second;
+  // built aside and entered only when every buffer exists (an allocation
+  // failure leaves no half-made entry behind)
+  std::unique_ptr<DevWork> Wp(new DevWork());
+  DevWork* W = Wp.get();
   W->n_rhs = n_rhs;
   W->fp64 = fp64;
   size_t es = fp64 ? 8 : 4;
@@ -425,6 +435,7 @@ static DevWork* work_for(DevForest& F, bool fp64, int n_rhs, bool grad = false) 
   W->pot = static_cast<double*>(alloc_bytes(size_t(n_rhs) * (grad ? 4 : 1) * F.ntgt * 8));
   if (grad && !fp64) W->dn_chk64 = static_cast<double*>(alloc_bytes(cols * 8));
   W->absmax = static_cast<unsigned*>(alloc_bytes(16));
+  F.work[key] = Wp.release();
   return W;
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <memory>
 #include <set>
 
 #include "common.hpp"
@@ -62,7 +63,8 @@ void check_operand_limits(int64_t nbox, int n_rhs, int n) {
 
 HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops, int TB, int TBm,
                          bool split, double pair_fill, int64_t max_pairs, bool per_level) {
-  auto* Fp = new HostForest();
+  alloc_hook("evaluate (plans)");
+  std::unique_ptr<HostForest> Fp(new HostForest());
   HostForest& F = *Fp;
   F.nprob = n;
   F.src_off.assign(n + 1, 0);
@@ -431,7 +433,7 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
       F.pair_off.push_back(int32_t(F.pair_items.size()));
     }
   }
-  return Fp;
+  return Fp.release();
 }
 
 }  // namespace kifmm

@@ -361,6 +361,7 @@ HostTree* build_host_tree(const double* src, int64_t nsrc, const double* tgt, in
   for (int64_t i = 0; i < 3 * ntgt; ++i)
     if (!std::isfinite(tgt[i])) raise(KIFMM_EINVAL, "build_tree: non-finite target coordinate");
 
+  alloc_hook("build_tree");
   auto* Tp = new HostTree();
   HostTree& T = *Tp;
   try {

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <string>
 #include <vector>
 
 #include "common.hpp"
@@ -205,8 +206,10 @@ __device__ inline int64_t lower_bound_u64(const u64* a, int64_t n, u64 v) {
 
 template <class T>
 T* dalloc(std::vector<void*>& owned, size_t count) {
+  alloc_hook("hipMalloc");
   void* p = nullptr;
-  HIPCHECK(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)));
+  const hipError_t e = hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
   owned.push_back(p);
   return static_cast<T*>(p);
 }

@@ -147,6 +147,7 @@ HostOps* build_host_ops(int p, double rcond, bool device_svd, double kappa, doub
     if (!(r0 > 0.0) || !std::isfinite(r0)) raise(KIFMM_EINVAL, "precompute_operators: root half-width must be > 0");
     if (max_level < 2 || max_level > 20) raise(KIFMM_EINVAL, "precompute_operators: max_level must be in [2, 20]");
   }
+  alloc_hook("precompute_operators");
   auto* O = new HostOps();
   try {
     O->p = p;
@@ -280,6 +281,7 @@ void save_host_ops(const HostOps& O, const char* path) {
 
 HostOps* load_host_ops(const char* path, int p, double rcond) {
   if (!path) raise(KIFMM_EINVAL, "ops_load: null path");
+  alloc_hook("ops_load");
   FILE* f = std::fopen(path, "rb");
   if (!f) raise(KIFMM_EINVAL, std::string("ops_load: cannot read ") + path);
   std::unique_ptr<HostOps> O(new HostOps());

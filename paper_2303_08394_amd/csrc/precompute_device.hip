@@ -56,8 +56,10 @@ std::vector<double> pinv_truncated_device(const double* a, int n, double rcond, 
     }
   } guard{bufs};
   auto alloc = [&](size_t bytes) {
+    alloc_hook("precompute (device)");
     void* p = nullptr;
-    HIPCHECK(hipMalloc(&p, bytes));
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("precompute (device): hipMalloc: ") + hipGetErrorString(e));
     bufs.push_back(p);
     return static_cast<double*>(p);
   };
@@ -110,8 +112,10 @@ std::vector<double> m2l_check_form_device(const HostOps& O) {
     }
   } guard{bufs};
   auto alloc = [&](size_t bytes) {
+    alloc_hook("precompute (device)");
     void* p = nullptr;
-    HIPCHECK(hipMalloc(&p, bytes));
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("precompute (device): hipMalloc: ") + hipGetErrorString(e));
     bufs.push_back(p);
     return static_cast<double*>(p);
   };

@@ -449,6 +449,7 @@ struct Pool {
   std::vector<void*> owned;
   template <class T>
   T* get(int64_t count) {
+    alloc_hook("build_tree_device");
     void* p = nullptr;
     const hipError_t e = hipMalloc(&p, size_t(std::max<int64_t>(count, 1)) * sizeof(T));
     if (e != hipSuccess) raise(KIFMM_ENOMEM, std::string("build_tree_device: hipMalloc: ") + hipGetErrorString(e));

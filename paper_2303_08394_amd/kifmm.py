@@ -49,7 +49,7 @@ EXPORTED = [
     "kifmm_ops_export", "kifmm_ops_n", "kifmm_ops_levels", "kifmm_evaluate", "kifmm_evaluate_noalloc",
     "kifmm_evaluate_gradient", "kifmm_evaluate_batch",
     "kifmm_evaluate_simple", "kifmm_set_profiling", "kifmm_n_phases", "kifmm_phase_name",
-    "kifmm_get_phase_times", "kifmm_graph_captures", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
+    "kifmm_get_phase_times", "kifmm_graph_captures", "kifmm_debug_fail_allocations", "kifmm_debug_buffer", "kifmm_set_tuning", "kifmm_get_tuning", "kifmm_tree_destroy", "kifmm_ops_destroy", "kifmm_last_error",
 ]
 
 
@@ -94,6 +94,8 @@ def lib():
     L.kifmm_get_phase_times.argtypes = [D, C.POINTER(I64)]
     L.kifmm_graph_captures.argtypes = []
     L.kifmm_graph_captures.restype = I64
+    L.kifmm_debug_fail_allocations.argtypes = [I64]
+    L.kifmm_debug_fail_allocations.restype = None
     L.kifmm_debug_buffer.argtypes = [P, I32, I32, I32, D, I64]
     L.kifmm_set_tuning.argtypes = [C.c_char_p, I32]
     L.kifmm_get_tuning.argtypes = [C.c_char_p, C.POINTER(I32)]
@@ -104,7 +106,7 @@ def lib():
     L.kifmm_last_error.restype = C.c_char_p
     for name in EXPORTED:
         if name not in ("kifmm_ops_n", "kifmm_n_phases", "kifmm_phase_name", "kifmm_last_error",
-                        "kifmm_graph_captures",
+                        "kifmm_graph_captures", "kifmm_debug_fail_allocations",
                         "kifmm_tree_destroy", "kifmm_ops_destroy"):
             getattr(L, name).restype = C.c_int
     _lib = L
@@ -449,6 +451,12 @@ def get_tuning(key: str) -> int:
 
 def set_profiling(on: bool):
     _check(lib().kifmm_set_profiling(1 if on else 0))
+
+
+def fail_allocations_after(n: int):
+    """Test hook: the allocation after n more successful ones fails with
+    ENOMEM (kifmm_debug_fail_allocations); n < 0 disarms it."""
+    lib().kifmm_debug_fail_allocations(int(n))
 
 
 def graph_captures() -> int:

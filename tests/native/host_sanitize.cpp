@@ -127,6 +127,31 @@ int main() {
     CHECK(threw);
   }
 
+  // injected allocation failures: ENOMEM, nothing leaked (leak detection on),
+  // the hook disarmed after firing
+  {
+    auto enomem = [](auto&& f) {
+      alloc_fail_counter() = 0;
+      bool threw = false;
+      try {
+        f();
+      } catch (const Error& e) {
+        threw = e.status == KIFMM_ENOMEM;
+      }
+      return threw && alloc_fail_counter() == -1;
+    };
+    auto x = cube(3000, 9);
+    CHECK(enomem([&] { std::unique_ptr<HostTree> t(build_host_tree(x.data(), 3000, x.data(), 3000, params(-1, 16, 8, true))); }));
+    CHECK(enomem([&] { std::unique_ptr<HostOps> o(build_host_ops(3, 1e-9)); }));
+    std::unique_ptr<HostOps> o3(build_host_ops(3, 1e-9));
+    const HostTree* one = trees[0].get();
+    CHECK(enomem([&] { std::unique_ptr<HostForest> f(build_forest(&one, 1, *o3, 64, 64, true, 0.4, 1 << 30)); }));
+    alloc_fail_counter() = 3;  // armed, not reached by one build
+    std::unique_ptr<HostTree> t(build_host_tree(x.data(), 3000, x.data(), 3000, params(-1, 16, 8, true)));
+    CHECK(alloc_fail_counter() == 2);
+    alloc_fail_counter() = -1;
+  }
+
   // density columns the GEMM can address with 32-bit counts of 16-byte units
   {
     auto refused = [](int64_t nbox, int n_rhs, int n) {

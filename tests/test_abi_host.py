@@ -297,3 +297,33 @@ def test_screened_tables_match_oracle_per_level():
         oc = (1, 0, 1)
         np.testing.assert_allclose(m2m[lev, 5], r * o.m2m(lev + 1, oc), rtol=1e-12)
         np.testing.assert_allclose(l2l[lev, 5], r * o.l2l(lev, oc), rtol=1e-12)
+
+
+def test_injected_allocation_failures_on_the_host(tmp_path):
+    """The allocation-failure hook (kifmm_debug_fail_allocations): a tree
+    build, a precompute and a cache load fail with ENOMEM when their
+    allocation point is hit, leave nothing behind, and work again once the
+    hook has fired (it disarms itself)."""
+    import ctypes as C
+    L = K.lib()
+    x, _ = I.uniform_cube(2000, seed=12)
+    prm = K._params(2, 8, 4, True, (0.5, 0.5, 0.5), 0.5)
+    h = C.c_void_p()
+    K.fail_allocations_after(0)
+    assert L.kifmm_build_tree(K._dptr(x), len(x), K._dptr(x), len(x), C.byref(prm), C.byref(h)) == 2
+    assert b"injected" in L.kifmm_last_error() and not h.value
+    t = K.Tree(x, uniform_depth=2, **CUBE)  # disarmed after firing
+    assert t.info().n_src == 2000
+    K.fail_allocations_after(0)
+    with pytest.raises(K.KifmmError, match="ENOMEM"):
+        K.Operators(3)
+    ops = K.Operators(3)
+    path = str(tmp_path / "ops.bin")
+    ops.save(path)
+    K.fail_allocations_after(0)
+    with pytest.raises(K.KifmmError, match="ENOMEM"):
+        K.Operators.load(path, 3)
+    assert K.Operators.load(path, 3).n == ops.n
+    K.fail_allocations_after(5)  # armed but not reached by the host build
+    K.Tree(x, uniform_depth=2, **CUBE)
+    K.fail_allocations_after(-1)
