@@ -44,6 +44,9 @@ PEAK_HBM = 8.0e12
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_PAIR = 37.0 / 4.0
 PEAK_PAIRS = VALU_LANE_OPS / SLOTS_PER_PAIR
+# A second, tighter bound: the minimal pair itself, 8 issue slots (3 sub,
+# mul + 2 fma for r^2, rsqrt, fma for the sum), no loop overhead.
+PEAK_PAIRS_MIN_OPS = VALU_LANE_OPS / 8.0
 
 
 def _work_counts(tree, pn):
@@ -409,12 +412,14 @@ def main():
     # the particle kernels, reported beside the dominant one
     if ms.get("near", 0.0) > 0.0:
         near_rate = near_pairs * n_rhs / (ms["near"] / max(launches["near"], 1) * 1e-3)
-        result["near_field"] = {"pairs_per_s": near_rate, "frac_of_valu_peak": near_rate / PEAK_PAIRS}
+        result["near_field"] = {"pairs_per_s": near_rate, "frac_of_valu_peak": near_rate / PEAK_PAIRS,
+                                "frac_of_min_op_bound": near_rate / PEAK_PAIRS_MIN_OPS}
     else:
         # near and far field of the leaves in one kernel (the "far" phase)
         leaf_rate = leaf_pairs / (ms["far"] / max(launches["far"], 1) * 1e-3)
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
-                                "frac_of_valu_peak": leaf_rate / PEAK_PAIRS}
+                                "frac_of_valu_peak": leaf_rate / PEAK_PAIRS,
+                                "frac_of_min_op_bound": leaf_rate / PEAK_PAIRS_MIN_OPS}
     # the committed counter summaries are per M2L tile width (two parity parts
     # per tile, gathered tiles: the layouts whose M2L kernel they measured)
     m2l_counters = (args.config == "uniform_1m" and dom == "m2l" and layout["m2l_split"] == 1

@@ -372,6 +372,16 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     both adding into the zeroed output with atomics; each
  *                     output is then the sum of two terms, so results stay
  *                     bitwise reproducible.  0: one block per tile.
+ *   "m2l_wide":       1: split-BF16 and split-FP16 M2L plans of 65..128
+ *                     columns (m2l_tile_cols 128) run a kernel whose waves
+ *                     own 80 x 64 outputs and take the densities from global
+ *                     memory straight into registers; 0 (default): the
+ *                     general gathered-GEMM kernel.  Results are bitwise
+ *                     equal.
+ *   "m2l_rows":       operator rows per M2L block: 160, 128, or 0 (default)
+ *                     for the one that pads the operator's rows (n rounded
+ *                     up to 32) the least: 128 at p = 4, 5, 7, 10.  Results
+ *                     are bitwise equal.
  *   "near_fork":      4 (default): near field (P2P) and far field (L2P,
  *                     M2P) of each leaf are summed by one kernel at the end
  *                     of the evaluation.  0..3: the near field runs as its

@@ -4,7 +4,9 @@ The layout knobs of ``kifmm_set_tuning`` change how an evaluation is cut into
 kernel launches, not the method: the M2L tile width (64, 128 or 192 output
 columns per block; results bitwise equal), whether each M2L tile runs as one
 block or as two parity parts, the tile-fill threshold below which a problem's
-M2L runs pair by pair, and where the near field sits in the schedule.  Which
+M2L runs pair by pair, where the near field sits in the schedule, and the
+shape of the M2L block (160 or 128 operator rows; for 128-column split tiles
+the kernel with 80 x 64 wave tiles; results bitwise equal).  Which
 layout is fastest depends on the workload (uniform or adaptive tree, points
 per leaf, order p, right-hand sides) and on the device, so it is measured:
 ``search`` times each candidate on the caller's own evaluation, with HIP events
@@ -35,6 +37,10 @@ SPACE: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("m2l_split", (1, 0)),
     ("m2l_pair_fill", (40, 0, 101)),
     ("near_fork", (4, 2, 0)),
+    # the M2L block's shape: operator rows per block (0: fewest padded rows),
+    # and for 128-column split tiles the wide-tile kernel (80 x 64 wave tiles)
+    ("m2l_rows", (0, 160, 128)),
+    ("m2l_wide", (0, 1)),
 )
 
 

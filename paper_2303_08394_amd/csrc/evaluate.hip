@@ -1771,6 +1771,210 @@ __global__ __launch_bounds__(256 * CG, (GemmOcc<MODE, TO, CB, TAG, CG>::MINB)) v
 // pipeline
 // ------------------------------------------------------------------------
 
+// Split-precision M2L with wide tiles (BF16x3 and FP16x3: two operator parts,
+// two density parts).  A block owns 160 rows x 128 output columns; its four
+// waves each own 80 rows x 64 columns (5 x 4 MFMA blocks of 16 x 16), so a
+// wave reads 10 KB of operator fragments from LDS per 60 MFMAs instead of
+// 14 KB per 30 in gemm_kernel's 80 x 32 wave tiles.  Only the operator goes
+// through LDS, double-buffered (one barrier per 32-wide k chunk); every lane
+// loads its density fragments (8 consecutive k of one column, both parts)
+// straight from the chunk-interleaved split operand into registers, one
+// chunk ahead.  Same plans, same arithmetic and summation order per column
+// as gemm_kernel, so the results are bitwise equal to it.
+template <int MODE, class TO>
+__global__ __launch_bounds__(256, 2) void m2l_wide_kernel(GemmArgs a) {
+  using G = GT<MODE>;
+  using TA = typename G::TA;
+  static_assert(G::NB == 2 && (MODE == GM_BF3 || MODE == GM_H3), "two density parts");
+  using Cfg = GemmCfg<MODE, TA, TO, 2, 1, kRB>;  // the operator side of the 160-row tile
+  constexpr int KC = 32, RBW = kRB / 2, CBW = 4, NT = 256;
+  constexpr int A_BYTES = Cfg::A_ELEMS * int(sizeof(TA));
+  using vec8 = typename std::conditional<MODE == GM_H3, f16x8, bf16x8>::type;
+  __shared__ __align__(16) unsigned char smem[2 * A_BYTES];
+  __shared__ int s_ops[kMaxTileSteps];
+  float out_scale = 1.0f;
+  if constexpr (MODE == GM_H3) out_scale = ldexpf(1.0f, -f16_density_exp(a.absmax) - kF16OpExp);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tile = blockIdx.x;
+  const int row0 = blockIdx.y * Cfg::ROWS;
+  const int nrb = min(kRB, (a.ld - row0) / 16);
+  const int ld = a.ld;
+  const int ncols = a.TB * a.n_rhs;
+  const int sb = a.step_beg[tile], se = a.step_beg[tile + 1];
+  const int kcs = ld / KC;
+  const int nchunks = (se - sb) * kcs;
+
+  f32x4 acc[RBW][CBW];
+#pragma unroll
+  for (int i = 0; i < RBW; ++i)
+#pragma unroll
+    for (int c = 0; c < CBW; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][c][v] = 0.0f;
+
+  // operator staging: the same units and LDS slots as gemm_kernel's
+  int a_goff[Cfg::A_PER_T], a_loff[Cfg::A_PER_T];
+#pragma unroll
+  for (int j = 0; j < Cfg::A_PER_T; ++j) {
+    const int u = (tid + j * NT) % Cfg::A_UNITS;
+    const int part = u % Cfg::CPR, rsub = (u / Cfg::CPR) & 1, t = (u / (2 * Cfg::CPR)) % 2;
+    const int rl = (u / (2 * Cfg::CPR * 2)) * 2 + rsub;
+    const int rg = min(row0 + rl, ld - 1);
+    a_goff[j] = rg * ld * 2 + t * KC + part * Cfg::EPC;
+    a_loff[j] = t * Cfg::A_TSTRIDE + Cfg::off(rl, part);
+  }
+  u32x4 ra[Cfg::A_PER_T];
+  // density fragments of two chunks: [set][column block][part]
+  u32x4 rb[2][CBW][2];
+  const u32x4* inb = static_cast<const u32x4*>(a.in);
+  const uint32_t col_units = uint32_t(ld * 2 * int(sizeof(TA)) / 16);  // 16-byte units per column
+  // the lane's column of each column block (within the tile), and the 16-byte
+  // unit of its k group in that column of the step being loaded
+  // (the source boxes of the next step are fetched a whole step ahead)
+  uint32_t b_base[CBW];
+  int nxt_src[CBW];
+  int ld_st = sb, ld_kc = 0;  // step and chunk of the chunk being loaded
+  int cur_op = 0;
+  auto fetch_src = [&](int st) __attribute__((always_inline)) {
+    const int sc = min(st, se - 1);
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+      const int s = wc * 64 + c * 16 + r16;
+      nxt_src[c] = s < ncols ? a.step_src[int64_t(sc) * a.TB + s / a.n_rhs] : a.zero_box;
+    }
+  };
+  auto begin_step = [&]() __attribute__((always_inline)) {
+    cur_op = s_ops[min(ld_st, se - 1) - sb];
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+      const int s = wc * 64 + c * 16 + r16;
+      b_base[c] = (uint32_t(nxt_src[c]) * uint32_t(a.n_rhs) + uint32_t(s % a.n_rhs)) * col_units + uint32_t(g);
+    }
+  };
+  auto load = [&](int set) __attribute__((always_inline)) {
+    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + 2 * (ld_kc * KC);
+#pragma unroll
+    for (int j = 0; j < Cfg::A_PER_T; ++j) ra[j] = *reinterpret_cast<const u32x4*>(opb + a_goff[j]);
+#pragma unroll
+    for (int c = 0; c < CBW; ++c)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) rb[set][c][t] = inb[b_base[c] + uint32_t(ld_kc * 8 + t * 4)];
+  };
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++ld_kc == kcs) {
+      ld_kc = 0;
+      ++ld_st;
+      begin_step();
+      fetch_src(ld_st + 1);
+    }
+  };
+  auto store_a = [&](int buf) __attribute__((always_inline)) {
+    TA* As = reinterpret_cast<TA*>(smem + buf * A_BYTES);
+#pragma unroll
+    for (int j = 0; j < Cfg::A_PER_T; ++j) *reinterpret_cast<u32x4*>(As + a_loff[j]) = ra[j];
+  };
+  auto mma = [](vec8 x, vec8 y, f32x4 c) __attribute__((always_inline)) {
+    if constexpr (MODE == GM_H3) return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  };
+  auto compute = [&](int buf, int set) __attribute__((always_inline)) {
+    const TA* As = reinterpret_cast<const TA*>(smem + buf * A_BYTES);
+#pragma unroll
+    for (int i = 0; i < RBW; ++i) {
+      const int o = Cfg::off((wr * RBW + i) * 16 + r16, g);
+      const vec8 ah = *reinterpret_cast<const vec8*>(As + o);
+      const vec8 al = *reinterpret_cast<const vec8*>(As + Cfg::A_TSTRIDE + o);
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) {
+        const vec8 bh = __builtin_bit_cast(vec8, rb[set][c][0]);
+        const vec8 bl = __builtin_bit_cast(vec8, rb[set][c][1]);
+        acc[i][c] = mma(ah, bh, acc[i][c]);
+        acc[i][c] = mma(al, bh, acc[i][c]);
+        acc[i][c] = mma(ah, bl, acc[i][c]);
+      }
+    }
+  };
+
+  if (nchunks > 0) {
+    for (int i = tid; i < se - sb; i += NT) s_ops[i] = a.step_op[sb + i];
+    __syncthreads();
+    fetch_src(sb);
+    begin_step();
+    fetch_src(sb + 1);
+    load(0);
+    store_a(0);
+    if (nchunks > 1) {
+      advance();
+      load(1);
+    }
+    __syncthreads();
+    // chunk c: computed from LDS buffer c % 2 and register set c % 2; its
+    // operator for chunk c + 1 goes to the other buffer, then chunk c + 2 is
+    // loaded into the freed register set
+    const std::integral_constant<int, 0> S0;
+    const std::integral_constant<int, 1> S1;
+    auto iteration = [&](int c, auto SET) __attribute__((always_inline)) {
+      constexpr int set = decltype(SET)::value;
+      compute(set, set);
+      if (c + 1 < nchunks) store_a(set ^ 1);
+      if (c + 2 < nchunks) {
+        advance();
+        load(set);
+      }
+      __syncthreads();
+    };
+    int c = 0;
+    for (; c + 1 < nchunks; c += 2) {
+      iteration(c, S0);
+      iteration(c + 1, S1);
+    }
+    if (c < nchunks) iteration(c, S0);
+  }
+
+#pragma unroll
+  for (int cb = 0; cb < CBW; ++cb) {
+    const int s = wc * 64 + cb * 16 + r16;
+    if (s < ncols) {
+      const int b = s / a.n_rhs, r = s % a.n_rhs;
+      const int box = a.tile_cols[int64_t(tile) * a.TB + b];
+      if (box >= 0) {
+        TO* o = static_cast<TO*>(a.out) + (int64_t(box) * a.n_rhs + r) * ld;
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+          if (wr * RBW + i < nrb) {
+            const int rbase = row0 + (wr * RBW + i) * 16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              float val = acc[i][cb][v];
+              if constexpr (MODE == GM_H3) val *= out_scale;
+              unsafeAtomicAdd(o + rbase + G::row(lane, v), TO(val));
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Split-precision M2L plans of 65..128 columns run m2l_wide_kernel (1) or
+// gemm_kernel (0); the two give bitwise equal results.
+static bool g_m2l_wide = false;
+void set_m2l_wide(bool on) { g_m2l_wide = on; }
+
+// Operator rows per M2L block: 160 or 128, or 0 to take the one that pads
+// the operator's ld rows the least (160 at ld = 160 and 320; 128 at ld = 64,
+// 128, 224 and 512, i.e. p = 4, 5, 7 and 10).  Rows are independent
+// outputs, so the choice does not change any result.
+static int g_m2l_rows = 0;
+void set_m2l_rows(int rows) { g_m2l_rows = rows; }
+static int m2l_block_rows(int ld) {
+  if (g_m2l_rows) return g_m2l_rows;
+  const int c160 = (ld + 159) / 160 * 160, c128 = (ld + 127) / 128 * 128;
+  return c128 < c160 ? 128 : 160;
+}
+
 // 16-byte units spanned by the input columns of a gathered GEMM (boxes
 // 0..zero_box, n_rhs columns each of ld rows, split modes NB parts a row)
 template <int MODE, class TI>
@@ -1796,29 +2000,50 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
     raise(KIFMM_EUNSUPPORTED, "GEMM operand beyond 64 GiB (boxes x right-hand sides x rows)");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
-  dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
+  // split-precision M2L tiles of 65..128 columns: the wide-tile kernel
+  if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && TAG == 1) {
+    if (g_m2l_wide && ncols > 64 && ncols <= 128 && P.atomic) {
+      dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
+      hipLaunchKernelGGL((m2l_wide_kernel<MODE, TO>), grid, dim3(256), 0, s, g);
+      LAUNCHCHECK("m2l_wide_kernel");
+      ps.launches++;
+      return;
+    }
+  }
   // plans with few tiles (the coarse levels of M2M, L2L and the solves) run
   // 32-row blocks: five times the blocks, a fifth of the work per block
   if constexpr (TAG == 0) {
     if (P.ntile < kFewTiles && ncols <= 64) {
-      grid.y = (ld + 31) / 32;
+      dim3 grid(P.ntile, (ld + 31) / 32);
       hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 1, 2>), grid, dim3(256), 0, s, g);
       LAUNCHCHECK("gemm_kernel");
       ps.launches++;
       return;
     }
   }
-  if (ncols > 128) {
-    if constexpr (GemmOcc<MODE, TO, 1, TAG, 3>::WIDE_OK) {
-      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 3>), grid, dim3(768), 0, s, g);
+  // blocks of RB x 16 operator rows: 160 (10 row blocks) or, for M2L, 128
+  // rows where fewer padded rows result (see m2l_block_rows)
+  auto dispatch = [&](auto rb_tag) {
+    constexpr int RB = decltype(rb_tag)::value;
+    dim3 grid(P.ntile, (ld + RB * 16 - 1) / (RB * 16));
+    if (ncols > 128) {
+      if constexpr (GemmOcc<MODE, TO, 1, TAG, 3>::WIDE_OK) {
+        hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 3, RB>), grid, dim3(768), 0, s, g);
+      } else {
+        grid.z = (ncols + 63) / 64;  // 64-column slices of the wide tiles
+        hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 1, RB>), grid, dim3(256), 0, s, g);
+      }
+    } else if (ncols > 64) {
+      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG, 1, RB>), grid, dim3(256), 0, s, g);
     } else {
-      grid.z = (ncols + 63) / 64;  // 64-column slices of the wide tiles
-      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG, 1, RB>), grid, dim3(256), 0, s, g);
     }
-  } else if (ncols > 64) {
-    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 2, TAG>), grid, dim3(256), 0, s, g);
+  };
+  if constexpr (TAG != 0) {
+    if (m2l_block_rows(ld) == 128) dispatch(std::integral_constant<int, 8>());
+    else dispatch(std::integral_constant<int, kRB>());
   } else {
-    hipLaunchKernelGGL((gemm_kernel<MODE, TI, TO, 1, TAG>), grid, dim3(256), 0, s, g);
+    dispatch(std::integral_constant<int, kRB>());
   }
   LAUNCHCHECK("gemm_kernel");
   ps.launches++;
@@ -2243,6 +2468,8 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_check_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_near_fork)),
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_wide)),
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_rows)),
                                   reinterpret_cast<const void*>(intptr_t(grad))};
   for (int k = 0; k < F.nprob; ++k) {
     key.push_back(charges[k]);

@@ -280,6 +280,57 @@ def test_wide_m2l_tiles_equal_narrow(precision):
     assert rel(wide, want) < TOL32
 
 
+@pytest.mark.parametrize("case", [("uniform20k_d3_p6", 1), ("uniform20k_d3_p6", 2), ("uniform20k_d3_p6", 3),
+                                  ("uniform3k_d3_p4_sparse", 1), ("clustered8k_nc24_p5", 1), ("p8", 1)])
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp64+m2l_f16x3"])
+def test_wide_tile_kernel_equals_gemm_kernel(case, precision):
+    """The wide-tile split M2L kernel (128-column plans) gives gemm_kernel's
+    results bitwise: the same plans, products and per-column summation order.
+    Cases cover 1, 2 and 3 right-hand sides (tiles of 128, 64 and 42 boxes:
+    ragged columns), operators shorter than the 160-row block (p = 4, 5),
+    two row blocks (p = 8), adaptive trees, and FP64 outputs."""
+    name, n_rhs = case
+    if name == "p8":
+        x, q = I.uniform_cube(12000, seed=33, charge_range=(-1, 1))
+        tgt, p, kw = None, 8, dict(uniform_depth=3, **CUBE)
+    else:
+        x, q, tgt, p, kw = CASES[name]()
+    tree = K.Tree(x, tgt, **kw)
+    qm = np.vstack([np.atleast_2d(q)] + [np.random.default_rng(40 + r).uniform(-1, 1, (1, len(x)))
+                                         for r in range(n_rhs - 1)])
+    K.set_tuning("m2l_tile_cols", 128)
+    try:
+        K.set_tuning("m2l_wide", 0)
+        ref = gpu_eval(tree, p, qm, precision)
+        K.set_tuning("m2l_wide", 1)
+        got = gpu_eval(tree, p, qm, precision)
+    finally:
+        K.set_tuning("m2l_tile_cols", 64)
+        K.set_tuning("m2l_wide", 0)
+    np.testing.assert_array_equal(got, ref)
+    narrow = gpu_eval(tree, p, qm, precision)
+    np.testing.assert_array_equal(got, narrow)
+
+
+@pytest.mark.parametrize("p", [5, 6, 7])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "f16x3", "fp64"])
+def test_m2l_block_rows_do_not_change_results(p, precision):
+    """M2L blocks of 160 or 128 operator rows (m2l_rows) give the same
+    potentials bitwise: rows are independent outputs.  p = 5 and 7 (ld 128,
+    224) default to 128-row blocks, p = 6 to 160."""
+    x, q = I.uniform_cube(6000, seed=34, charge_range=(-1, 1))
+    tree = K.Tree(x, uniform_depth=3, **CUBE)
+    outs = []
+    try:
+        for rows in (0, 160, 128):
+            K.set_tuning("m2l_rows", rows)
+            outs.append(gpu_eval(tree, p, q, precision))
+    finally:
+        K.set_tuning("m2l_rows", 0)
+    np.testing.assert_array_equal(outs[1], outs[0])
+    np.testing.assert_array_equal(outs[2], outs[0])
+
+
 @pytest.mark.parametrize("fork", [0, 1, 2, 3])
 @pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
 def test_near_field_schedules(fork, precision):
