@@ -204,6 +204,8 @@ def main():
                     help="problems whose M2L tiles are less full than this (percent) run M2L pair by pair")
     ap.add_argument("--near-fork", type=int, default=-1,
                     help="fork the near field after the gather (0) or before M2L (1)")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="set a tuning knob (kifmm_set_tuning) before anything runs; repeatable")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -218,6 +220,9 @@ def main():
     from paper_2303_08394_amd import inputs as I
     from paper_2303_08394_amd import kifmm as K
 
+    for kv in args.tune:
+        key, _, val = kv.partition("=")
+        K.set_tuning(key, int(val))
     if args.m2l_tile:
         K.set_tuning("m2l_tile_cols", args.m2l_tile)
     if args.m2l_pair_fill >= 0:
@@ -326,7 +331,7 @@ def main():
         tuning = {"chosen": tr.best, "start_ms": tr.start_ms, "best_ms": tr.best_ms,
                   "trials": len(tr.trials), "search_s": time.perf_counter() - t0}
         del touts
-    layout = {k: K.get_tuning(k) for k in ("m2l_tile_cols", "m2l_split", "m2l_pair_fill", "near_fork")}
+    layout = {k: K.get_tuning(k) for k in ("m2l_tile_cols", "m2l_split", "m2l_pair_fill", "near_fork", "m2l_async")}
     res, t_eager, phases = run(precision, args.steps, args.warmup)
     result = {"eager_profiled_ms_per_step": t_eager * 1e3, "layout": layout}
     if tuning is not None:
@@ -394,7 +399,9 @@ def main():
         peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
                 "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
         issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
-        roof = {"kernel": "gemm_kernel (M2L)", "bound": "mfma",
+        split_m2l = m2l_kind in ("bf16x3", "f16x3") and layout["m2l_tile_cols"] <= 128
+        name = "m2l_async_kernel" if split_m2l and layout["m2l_async"] else "gemm_kernel"
+        roof = {"kernel": f"{name} (M2L)", "bound": "mfma",
                 "achieved": flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s",
                 "issued_frac": issued * flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / peak}
@@ -424,7 +431,8 @@ def main():
     # per tile, gathered tiles: the layouts whose M2L kernel they measured)
     m2l_counters = (args.config == "uniform_1m" and dom == "m2l" and layout["m2l_split"] == 1
                     and layout["m2l_pair_fill"] != 101)
-    sfx = precision + ("" if layout["m2l_tile_cols"] == 64 else f"_tile{layout['m2l_tile_cols']}")
+    sfx = (precision + ("" if layout["m2l_tile_cols"] == 64 else f"_tile{layout['m2l_tile_cols']}")
+           + ("" if layout["m2l_async"] else "_regstaged"))
     roof["traffic"] = _measured_traffic(sfx) if m2l_counters else None
     if m2l_counters:
         # SQ_VALU_MFMA_BUSY_CYCLES over the launch's cycles, and the clock the

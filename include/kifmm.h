@@ -378,6 +378,13 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     memory straight into registers; 0 (default): the
  *                     general gathered-GEMM kernel.  Results are bitwise
  *                     equal.
+ *   "m2l_async":      1 (default): split-BF16 and split-FP16 M2L plans of
+ *                     up to 128 columns (m2l_tile_cols 64 or 128) run a
+ *                     kernel that stages operator and density chunks from
+ *                     global memory straight into LDS, two chunks in
+ *                     flight; 0: the general gathered-GEMM kernel (and, with
+ *                     m2l_wide, the wide-tile kernel).  Results are bitwise
+ *                     equal.
  *   "m2l_rows":       operator rows per M2L block: 160, 128, or 0 (default)
  *                     for the one that pads the operator's rows (n rounded
  *                     up to 32) the least: 128 at p = 4, 5, 7, 10.  Results

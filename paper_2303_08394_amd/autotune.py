@@ -6,7 +6,8 @@ columns per block; results bitwise equal), whether each M2L tile runs as one
 block or as two parity parts, the tile-fill threshold below which a problem's
 M2L runs pair by pair, where the near field sits in the schedule, and the
 shape of the M2L block (160 or 128 operator rows; for 128-column split tiles
-the kernel with 80 x 64 wave tiles; results bitwise equal).  Which
+the kernel with 80 x 64 wave tiles; results bitwise equal) and the staging of
+the split M2L kernel (straight into LDS or through registers; bitwise equal).  Which
 layout is fastest depends on the workload (uniform or adaptive tree, points
 per leaf, order p, right-hand sides) and on the device, so it is measured:
 ``search`` times each candidate on the caller's own evaluation, with HIP events
@@ -34,6 +35,8 @@ from . import kifmm as K
 # candidate of each is its library default.
 SPACE: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("m2l_tile_cols", (64, 128, 192)),
+    # the split M2L kernel: staging straight into LDS (1) or through registers
+    ("m2l_async", (1, 0)),
     ("m2l_split", (1, 0)),
     ("m2l_pair_fill", (40, 0, 101)),
     ("near_fork", (4, 2, 0)),

@@ -486,7 +486,7 @@ static kifmm_status set_tuning_impl(const char* key, int32_t value);
 // The values of the knobs whose state lives with the evaluation kernels, as
 // last set here (their defaults until then), for kifmm_get_tuning.
 static std::atomic<int> g_near_fork_set{4}, g_graph_set{1}, g_fp64_sum_min_p_set{10},
-    g_check_min_p_set{10}, g_far_fp64_min_p_set{10}, g_m2l_wide_set{0}, g_m2l_rows_set{0};
+    g_check_min_p_set{10}, g_far_fp64_min_p_set{10}, g_m2l_wide_set{0}, g_m2l_rows_set{0}, g_m2l_async_set{1};
 
 static std::atomic<int>* tuning_slot(const char* key) {
   static const struct {
@@ -501,7 +501,8 @@ static std::atomic<int>* tuning_slot(const char* key) {
                {"m2l_check_min_p", &g_check_min_p_set},
                {"far_fp64_min_p", &g_far_fp64_min_p_set},
                {"m2l_wide", &g_m2l_wide_set},
-               {"m2l_rows", &g_m2l_rows_set}};
+               {"m2l_rows", &g_m2l_rows_set},
+               {"m2l_async", &g_m2l_async_set}};
   for (const auto& sl : slots)
     if (std::strcmp(key, sl.key) == 0) return sl.v;
   return nullptr;
@@ -573,6 +574,11 @@ static kifmm_status set_tuning_impl(const char* key, int32_t value) {
   if (std::strcmp(key, "m2l_wide") == 0) {
     if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: m2l_wide must be 0 or 1");
     set_m2l_wide(value != 0);
+    return KIFMM_OK;
+  }
+  if (std::strcmp(key, "m2l_async") == 0) {
+    if (value != 0 && value != 1) return fail(KIFMM_EINVAL, "set_tuning: m2l_async must be 0 or 1");
+    set_m2l_async(value != 0);
     return KIFMM_OK;
   }
   return fail(KIFMM_EINVAL, std::string("set_tuning: unknown key ") + key);

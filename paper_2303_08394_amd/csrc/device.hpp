@@ -119,6 +119,7 @@ int64_t graph_captures();
 void set_near_fork(int v);
 // split-precision M2L plans of 65..128 columns on the wide-tile kernel (default off)
 void set_m2l_wide(bool on);
+void set_m2l_async(bool on);
 // operator rows per M2L block: 160, 128, or 0 = the one padding the least
 void set_m2l_rows(int rows);
 // smallest order at which FP32-accumulating M2L sums its steps in FP64

@@ -1958,6 +1958,233 @@ __global__ __launch_bounds__(256, 2) void m2l_wide_kernel(GemmArgs a) {
   }
 }
 
+// Split-precision M2L with asynchronous staging (BF16x3 and FP16x3, tiles of
+// 64 CB columns).  Operator and density chunks go from global memory
+// straight into LDS (global_load_lds, 16 bytes a lane, no registers on the
+// way) in two stages: while chunk c feeds the matrix cores from one stage,
+// chunk c + 1 lands in the other, and one barrier per chunk hands the stages
+// over.  With no staging registers, a wave reads all fragments of its chunk
+// first and then issues its MFMAs back to back.  Block shape (four waves in
+// a 2 x 2 grid, wave tiles of 80 x 32 CB), LDS layout, plans, arithmetic and
+// summation order per column are gemm_kernel's, so the results are bitwise
+// equal to it.
+//
+// LDS traffic is arranged in 1 KB blocks (16 rows or columns of one part,
+// 64 bytes each): a stage holds 2 RB operator blocks and 8 CB density
+// blocks, and wave w fills operator blocks w, w + 4, ... and the density
+// blocks (both parts) of column slots 16 w .. 16 w + 15, 16 w + 64 .. .  One
+// load instruction writes one block, lane i to its 16-byte slot i, so each
+// lane fetches the global chunk that the XOR swizzle of the layout puts in
+// that slot (the swizzle is an involution).
+template <int MODE, class TO, int RB, int CB>
+__global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
+  using G = GT<MODE>;
+  using TA = typename G::TA;
+  static_assert(G::NB == 2 && (MODE == GM_BF3 || MODE == GM_H3), "two density parts");
+  using Cfg = GemmCfg<MODE, TA, TO, CB, 1, RB>;
+  constexpr int KC = 32, RBW = RB / 2, CBW = 2 * CB, NT = 256;
+  static_assert(Cfg::KC == KC && Cfg::TC == 64 * CB && Cfg::CPR == 4, "64 CB columns, 64-byte LDS rows");
+  static_assert((2 * RB) % 4 == 0, "operator blocks are dealt evenly to the four waves");
+  constexpr int A_PER_W = 2 * RB / 4;
+  constexpr int BLK = 16 * KC;  // elements of a 1 KB block
+  constexpr int STAGE = Cfg::A_ELEMS + Cfg::B_ELEMS;
+  using vec8 = typename std::conditional<MODE == GM_H3, f16x8, bf16x8>::type;
+  __shared__ __align__(16) TA stage0[STAGE];
+  __shared__ __align__(16) TA stage1[STAGE];
+  __shared__ int s_ops[kMaxTileSteps];
+  float out_scale = 1.0f;
+  if constexpr (MODE == GM_H3) out_scale = ldexpf(1.0f, -f16_density_exp(a.absmax) - kF16OpExp);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int tile = blockIdx.x;
+  const int row0 = blockIdx.y * Cfg::ROWS;
+  const int nrb = min(RB, (a.ld - row0) / 16);
+  const int ld = a.ld;
+  const int ncols = a.TB * a.n_rhs;
+  const int sb = a.step_beg[tile], se = a.step_beg[tile + 1];
+  const int kcs = ld / KC;
+  const int nchunks = (se - sb) * kcs;
+
+  f32x4 acc[RBW][CBW];
+#pragma unroll
+  for (int i = 0; i < RBW; ++i)
+#pragma unroll
+    for (int c = 0; c < CBW; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][c][v] = 0.0f;
+
+  // operator blocks of this wave: element offsets in an operator (chunk 0)
+  // and the blocks' places in a stage.  Rows past ld are clamped to a valid
+  // row; they only feed output rows the epilogue discards.
+  uint32_t a_goff[A_PER_W];
+  int a_dst[A_PER_W];
+#pragma unroll
+  for (int j = 0; j < A_PER_W; ++j) {
+    const int q = wave + 4 * j, t = q / RB, rb = q % RB;
+    const int rl = rb * 16 + (lane >> 2);
+    const int rg = min(row0 + rl, ld - 1);
+    a_goff[j] = uint32_t(rg * ld * 2 + t * KC + Cfg::swz(rl, lane & 3) * Cfg::EPC);
+    a_dst[j] = t * Cfg::A_TSTRIDE + rb * BLK;
+  }
+  // density blocks: column slots 64 m + 16 wave + lane / 4 of the tile
+  int slot[CB];
+  uint32_t b_chunk[CB];
+#pragma unroll
+  for (int m = 0; m < CB; ++m) {
+    slot[m] = 64 * m + wave * 16 + (lane >> 2);
+    b_chunk[m] = uint32_t(Cfg::swz(slot[m], lane & 3));
+  }
+  const uint32_t col_units = uint32_t(ld * 2 * int(sizeof(TA)) / 16);  // 16-byte units per column
+  uint32_t b_goff[CB];  // 16-byte unit of the slot's column, chunk 0, part 0
+  // Step and chunk of the next chunk to request.  The operator index and the
+  // source boxes of the following step are fetched a whole step ahead (the
+  // step's loads complete at a handover, before they are used).  Slots past
+  // the tile's columns load the last column's boxes: they only feed output
+  // columns that the epilogue drops.
+  int ld_st = sb, ld_kc = 0, cur_op = 0, nxt_op = 0, nxt_src[CB];
+  auto fetch_step = [&](int st) __attribute__((always_inline)) {
+    const int sc = min(st, se - 1);
+    nxt_op = s_ops[sc - sb];
+#pragma unroll
+    for (int m = 0; m < CB; ++m) nxt_src[m] = a.step_src[int64_t(sc) * a.TB + min(slot[m] / a.n_rhs, a.TB - 1)];
+  };
+  auto begin_step = [&]() __attribute__((always_inline)) {
+    cur_op = nxt_op;
+#pragma unroll
+    for (int m = 0; m < CB; ++m)
+      b_goff[m] = (uint32_t(nxt_src[m]) * uint32_t(a.n_rhs) + uint32_t(slot[m] % a.n_rhs)) * col_units + b_chunk[m];
+  };
+  auto advance = [&]() __attribute__((always_inline)) {
+    if (++ld_kc == kcs) {
+      ld_kc = 0;
+      ++ld_st;
+      begin_step();
+      fetch_step(ld_st + 1);
+    }
+  };
+  // the loads of the chunk (ld_st, ld_kc) into stage S
+  auto issue = [&](auto S) __attribute__((always_inline)) {
+    TA* st = decltype(S)::value == 0 ? stage0 : stage1;
+    const TA* opb = static_cast<const TA*>(a.ops) + int64_t(cur_op) * a.op_stride + 2 * (ld_kc * KC);
+#pragma unroll
+    for (int j = 0; j < A_PER_W; ++j)
+      __builtin_amdgcn_global_load_lds((void*)(opb + a_goff[j]), (void*)(st + a_dst[j]), 16, 0, 0);
+#pragma unroll
+    for (int m = 0; m < CB; ++m) {
+      const u32x4* inb = static_cast<const u32x4*>(a.in) + b_goff[m] + uint32_t(ld_kc * 8);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        __builtin_amdgcn_global_load_lds((void*)(inb + 4 * t),
+                                         (void*)(st + Cfg::A_ELEMS + t * Cfg::B_TSTRIDE + (4 * m + wave) * BLK), 16, 0, 0);
+    }
+  };
+  // this wave's loads have landed, then every wave's (and every wave is done
+  // with the chunk before); no instruction crosses this point (the scheduler
+  // would otherwise move the MFMAs of the chunk before it behind the wait)
+  auto handover = [&]() __attribute__((always_inline)) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto mma = [](vec8 x, vec8 y, f32x4 c) __attribute__((always_inline)) {
+    if constexpr (MODE == GM_H3) return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  };
+  auto compute = [&](auto S) __attribute__((always_inline)) {
+    // the loads issued before stay ahead of this chunk's work
+    __builtin_amdgcn_sched_barrier(0);
+    const TA* As = decltype(S)::value == 0 ? stage0 : stage1;
+    const TA* Bs = As + Cfg::A_ELEMS;
+    vec8 bh[CBW], bl[CBW], ah[RBW], al[RBW];
+#pragma unroll
+    for (int c = 0; c < CBW; ++c) {
+      const int o = Cfg::off(wc * 16 * CBW + c * 16 + r16, g);
+      bh[c] = *reinterpret_cast<const vec8*>(Bs + o);
+      bl[c] = *reinterpret_cast<const vec8*>(Bs + Cfg::B_TSTRIDE + o);
+    }
+#pragma unroll
+    for (int i = 0; i < RBW; ++i) {
+      const int o = Cfg::off((wr * RBW + i) * 16 + r16, g);
+      ah[i] = *reinterpret_cast<const vec8*>(As + o);
+      al[i] = *reinterpret_cast<const vec8*>(As + Cfg::A_TSTRIDE + o);
+    }
+    // per accumulator A_h x_h, A_l x_h, A_h x_l (gemm_kernel's order);
+    // consecutive products go to different accumulators
+#pragma unroll
+    for (int i = 0; i < RBW; ++i)
+#pragma unroll
+      for (int c = 0; c < CBW; ++c) {
+        acc[i][c] = mma(ah[i], bh[c], acc[i][c]);
+        acc[i][c] = mma(al[i], bh[c], acc[i][c]);
+        acc[i][c] = mma(ah[i], bl[c], acc[i][c]);
+      }
+    // every fragment read first (in the order above, so the first products
+    // wait for the first reads only), then the products
+    __builtin_amdgcn_sched_group_barrier(0x100, 2 * (CBW + RBW), 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 3 * CBW * RBW, 0);
+  };
+
+  if (nchunks > 0) {
+    for (int i = tid; i < se - sb; i += NT) s_ops[i] = a.step_op[sb + i];
+    __syncthreads();
+    fetch_step(sb);
+    begin_step();
+    fetch_step(sb + 1);
+    const std::integral_constant<int, 0> S0;
+    const std::integral_constant<int, 1> S1;
+    issue(S0);
+    int c = 0;
+    for (; c + 1 < nchunks; c += 2) {
+      handover();
+      advance();
+      issue(S1);
+      compute(S0);
+      handover();
+      if (c + 2 < nchunks) {
+        advance();
+        issue(S0);
+      }
+      compute(S1);
+    }
+    if (c < nchunks) {
+      handover();
+      compute(S0);
+    }
+  }
+
+#pragma unroll
+  for (int cb = 0; cb < CBW; ++cb) {
+    const int s = wc * 16 * CBW + cb * 16 + r16;
+    if (s < ncols) {
+      const int b = s / a.n_rhs, r = s % a.n_rhs;
+      const int box = a.tile_cols[int64_t(tile) * a.TB + b];
+      if (box >= 0) {
+        TO* o = static_cast<TO*>(a.out) + (int64_t(box) * a.n_rhs + r) * ld;
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+          if (wr * RBW + i < nrb) {
+            const int rbase = row0 + (wr * RBW + i) * 16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              float val = acc[i][cb][v];
+              if constexpr (MODE == GM_H3) val *= out_scale;
+              unsafeAtomicAdd(o + rbase + G::row(lane, v), TO(val));
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// Split-precision M2L plans of up to 128 columns run m2l_async_kernel (1) or
+// gemm_kernel (0); the two give bitwise equal results.
+static bool g_m2l_async = true;
+void set_m2l_async(bool on) { g_m2l_async = on; }
+
 // Split-precision M2L plans of 65..128 columns run m2l_wide_kernel (1) or
 // gemm_kernel (0); the two give bitwise equal results.
 static bool g_m2l_wide = false;
@@ -2000,8 +2227,23 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
     raise(KIFMM_EUNSUPPORTED, "GEMM operand beyond 64 GiB (boxes x right-hand sides x rows)");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
-  // split-precision M2L tiles of 65..128 columns: the wide-tile kernel
+  // split-precision M2L tiles of up to 128 columns: the asynchronous-staging
+  // kernel or (65..128 columns) the wide-tile kernel
   if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && TAG == 1) {
+    if (g_m2l_async && ncols <= 128 && P.atomic) {
+      const dim3 g128(P.ntile, (ld + 127) / 128), g160(P.ntile, (ld + kROWS - 1) / kROWS);
+      const bool r128 = m2l_block_rows(ld) == 128;
+      if (ncols <= 64) {
+        if (r128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, 1>), g128, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, 1>), g160, dim3(256), 0, s, g);
+      } else {
+        if (r128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, 2>), g128, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, 2>), g160, dim3(256), 0, s, g);
+      }
+      LAUNCHCHECK("m2l_async_kernel");
+      ps.launches++;
+      return;
+    }
     if (g_m2l_wide && ncols > 64 && ncols <= 128 && P.atomic) {
       dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
       hipLaunchKernelGGL((m2l_wide_kernel<MODE, TO>), grid, dim3(256), 0, s, g);
@@ -2469,6 +2711,7 @@ void evaluate_forest(EvalState& st, const HostOps& hops, OpsCache& oc, const voi
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_fp64_sum_min_p)),
                                   reinterpret_cast<const void*>(intptr_t(g_near_fork)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_wide)),
+                                  reinterpret_cast<const void*>(intptr_t(g_m2l_async)),
                                   reinterpret_cast<const void*>(intptr_t(g_m2l_rows)),
                                   reinterpret_cast<const void*>(intptr_t(grad))};
   for (int k = 0; k < F.nprob; ++k) {

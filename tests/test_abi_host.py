@@ -199,13 +199,14 @@ def test_tuning_keys_validated():
     good = {"m2l_tile_cols": (64, 128, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
             "near_fork": (0, 1, 2, 3, 4), "graph": (0, 1), "m2l_fp64_sum_min_p": (2, 10, 17),
             "m2l_check_min_p": (2, 10, 17), "far_fp64_min_p": (2, 10, 17), "m2l_wide": (0, 1),
-            "m2l_rows": (0, 128, 160)}
+            "m2l_rows": (0, 128, 160), "m2l_async": (0, 1)}
     bad = {"m2l_tile_cols": (0, 96, 256), "m2l_split": (2, -1), "m2l_pair_fill": (-1, 102),
            "near_fork": (-1, 5), "graph": (2,), "m2l_fp64_sum_min_p": (1, 18),
            "m2l_check_min_p": (1, 18), "far_fp64_min_p": (1, 18), "m2l_wide": (2, -1),
-           "m2l_rows": (96, 1, -1)}
+           "m2l_rows": (96, 1, -1), "m2l_async": (2, -1)}
     defaults = {"m2l_tile_cols": 64, "m2l_split": 1, "m2l_pair_fill": 40, "near_fork": 4, "graph": 1,
-                "m2l_fp64_sum_min_p": 10, "m2l_check_min_p": 10, "far_fp64_min_p": 10, "m2l_wide": 0, "m2l_rows": 0}
+                "m2l_fp64_sum_min_p": 10, "m2l_check_min_p": 10, "far_fp64_min_p": 10, "m2l_wide": 0, "m2l_rows": 0,
+                "m2l_async": 1}
     try:
         for k, vs in good.items():
             for v in vs:

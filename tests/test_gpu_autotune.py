@@ -63,7 +63,7 @@ def test_autotuned_layout_keeps_the_results(name, precision, tmp_path):
         got = run(tree, ops, qd, precision)
         assert rel(got, want) < TOL[precision]
         # tile width and block shape keep every value bitwise
-        same = ("m2l_tile_cols", "m2l_rows", "m2l_wide")
+        same = ("m2l_tile_cols", "m2l_rows", "m2l_wide", "m2l_async")
         if all(r.best[k] == c[0] for k, c in A.SPACE if k not in same):
             np.testing.assert_array_equal(got, base)  # only bitwise-neutral knobs moved
         else:

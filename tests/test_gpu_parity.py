@@ -299,6 +299,7 @@ def test_wide_tile_kernel_equals_gemm_kernel(case, precision):
     qm = np.vstack([np.atleast_2d(q)] + [np.random.default_rng(40 + r).uniform(-1, 1, (1, len(x)))
                                          for r in range(n_rhs - 1)])
     K.set_tuning("m2l_tile_cols", 128)
+    K.set_tuning("m2l_async", 0)
     try:
         K.set_tuning("m2l_wide", 0)
         ref = gpu_eval(tree, p, qm, precision)
@@ -307,9 +308,43 @@ def test_wide_tile_kernel_equals_gemm_kernel(case, precision):
     finally:
         K.set_tuning("m2l_tile_cols", 64)
         K.set_tuning("m2l_wide", 0)
+        K.set_tuning("m2l_async", 1)
     np.testing.assert_array_equal(got, ref)
     narrow = gpu_eval(tree, p, qm, precision)
     np.testing.assert_array_equal(got, narrow)
+
+
+@pytest.mark.parametrize("case", [("uniform20k_d3_p6", 1), ("uniform20k_d3_p6", 2), ("uniform20k_d3_p6", 3),
+                                  ("uniform3k_d3_p4_sparse", 1), ("clustered8k_nc24_p5", 1), ("p8", 1),
+                                  ("p7", 2)])
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp64+m2l_f16x3"])
+@pytest.mark.parametrize("width", [64, 128])
+def test_async_staging_kernel_equals_gemm_kernel(case, precision, width):
+    """The split M2L kernel that stages chunks straight from global memory into
+    LDS (plans of 64 and 128 columns) gives gemm_kernel's results bitwise: the
+    same plans, products and per-column summation order.  Cases: 1, 2 and 3
+    right-hand sides (ragged columns: tiles of 21 or 42 boxes), operators
+    shorter than the block (p = 4), 128-row blocks (p = 5, 7), two row blocks
+    (p = 8), adaptive trees, FP64 outputs."""
+    name, n_rhs = case
+    if name in ("p8", "p7"):
+        x, q = I.uniform_cube(12000, seed=33, charge_range=(-1, 1))
+        tgt, p, kw = None, int(name[1]), dict(uniform_depth=3, **CUBE)
+    else:
+        x, q, tgt, p, kw = CASES[name]()
+    tree = K.Tree(x, tgt, **kw)
+    qm = np.vstack([np.atleast_2d(q)] + [np.random.default_rng(40 + r).uniform(-1, 1, (1, len(x)))
+                                         for r in range(n_rhs - 1)])
+    K.set_tuning("m2l_tile_cols", width)
+    try:
+        K.set_tuning("m2l_async", 0)
+        ref = gpu_eval(tree, p, qm, precision)
+        K.set_tuning("m2l_async", 1)
+        got = gpu_eval(tree, p, qm, precision)
+    finally:
+        K.set_tuning("m2l_async", 1)
+        K.set_tuning("m2l_tile_cols", 64)
+    np.testing.assert_array_equal(got, ref)
 
 
 @pytest.mark.parametrize("p", [5, 6, 7])
