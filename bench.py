@@ -399,7 +399,7 @@ def main():
         peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
                 "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
         issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
-        split_m2l = m2l_kind in ("bf16x3", "f16x3") and layout["m2l_tile_cols"] <= 128
+        split_m2l = m2l_kind in ("bf16x3", "f16x3") and layout["m2l_tile_cols"] <= 160
         name = "m2l_async_kernel" if split_m2l and layout["m2l_async"] else "gemm_kernel"
         roof = {"kernel": f"{name} (M2L)", "bound": "mfma",
                 "achieved": flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / 1e12,

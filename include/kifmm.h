@@ -334,10 +334,12 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
 /* Process-wide tuning knobs of the evaluation kernels (a change of a plan
  * knob rebuilds the plans at the next evaluate).
  *   "m2l_tile_cols":  output columns (box x right-hand side) per M2L tile,
- *                     64 (default), 128 or 192.  With 192, M2L kernels with
- *                     32-bit outputs run one 768-thread block per tile; the
- *                     others cover the tile with 64-column slices.  Results
- *                     are bitwise equal to those of 64-column tiles.
+ *                     64 (default), 128, 160 or 192.  Above 128, M2L kernels
+ *                     with 32-bit outputs run one 768-thread block per tile
+ *                     (split modes up to 160 columns: the kernel of
+ *                     m2l_async); the others cover the tile with 64-column
+ *                     slices.  Results are bitwise equal to those of
+ *                     64-column tiles.
  *   "far_fp64_min_p": smallest order p at which FP32-bulk modes evaluate the
  *                     equivalent-surface terms in FP64 (default 10; 2..17,
  *                     17 = never).
@@ -379,7 +381,7 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     general gathered-GEMM kernel.  Results are bitwise
  *                     equal.
  *   "m2l_async":      1 (default): split-BF16 and split-FP16 M2L plans of
- *                     up to 128 columns (m2l_tile_cols 64 or 128) run a
+ *                     up to 160 columns (m2l_tile_cols 64, 128, 160) run a
  *                     kernel that stages operator and density chunks from
  *                     global memory straight into LDS, two chunks in
  *                     flight; 0: the general gathered-GEMM kernel (and, with

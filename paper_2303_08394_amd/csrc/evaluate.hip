@@ -1959,46 +1959,54 @@ __global__ __launch_bounds__(256, 2) void m2l_wide_kernel(GemmArgs a) {
 }
 
 // Split-precision M2L with asynchronous staging (BF16x3 and FP16x3, tiles of
-// 64 CB columns).  Operator and density chunks go from global memory
-// straight into LDS (global_load_lds, 16 bytes a lane, no registers on the
-// way) in two stages: while chunk c feeds the matrix cores from one stage,
-// chunk c + 1 lands in the other, and one barrier per chunk hands the stages
-// over.  With no staging registers, a wave reads all fragments of its chunk
-// first and then issues its MFMAs back to back.  Block shape (four waves in
-// a 2 x 2 grid, wave tiles of 80 x 32 CB), LDS layout, plans, arithmetic and
-// summation order per column are gemm_kernel's, so the results are bitwise
-// equal to it.
+// 16 NCB columns: 64, 128 or 160).  Operator and density chunks go from
+// global memory straight into LDS (global_load_lds, 16 bytes a lane, no
+// registers on the way) in two stages: while chunk c feeds the matrix cores
+// from one stage, chunk c + 1 lands in the other, and one barrier per chunk
+// hands the stages over.  With no staging registers, a wave reads all
+// fragments of its chunk first and then issues its MFMAs back to back.
+// Block shape (four waves in a 2 x 2 grid, wave tiles of 8 RB x 8 NCB), plans,
+// arithmetic and summation order per column are gemm_kernel's, so the
+// results are bitwise equal to it.
 //
 // LDS traffic is arranged in 1 KB blocks (16 rows or columns of one part,
-// 64 bytes each): a stage holds 2 RB operator blocks and 8 CB density
-// blocks, and wave w fills operator blocks w, w + 4, ... and the density
-// blocks (both parts) of column slots 16 w .. 16 w + 15, 16 w + 64 .. .  One
-// load instruction writes one block, lane i to its 16-byte slot i, so each
-// lane fetches the global chunk that the XOR swizzle of the layout puts in
-// that slot (the swizzle is an involution).
-template <int MODE, class TO, int RB, int CB>
+// 64 bytes each): a stage holds 2 RB operator blocks and 2 NCB density
+// blocks (80 KB a block at RB = NCB = 10, so two blocks fill a CU's 160 KB),
+// and wave w fills operator blocks w, w + 4, ... and the density blocks
+// (both parts) of column blocks w, w + 4, w + 8.  One load instruction
+// writes one block, lane i to its 16-byte slot i, so each lane fetches the
+// global chunk that the XOR swizzle of the layout puts in that slot (the
+// swizzle is an involution).
+template <int MODE, class TO, int RB, int NCB>
 __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
   using G = GT<MODE>;
   using TA = typename G::TA;
   static_assert(G::NB == 2 && (MODE == GM_BF3 || MODE == GM_H3), "two density parts");
-  using Cfg = GemmCfg<MODE, TA, TO, CB, 1, RB>;
-  constexpr int KC = 32, RBW = RB / 2, CBW = 2 * CB, NT = 256;
-  static_assert(Cfg::KC == KC && Cfg::TC == 64 * CB && Cfg::CPR == 4, "64 CB columns, 64-byte LDS rows");
+  static_assert(G::KC == 32 && sizeof(TA) == 2, "64-byte LDS rows");
+  static_assert(NCB % 2 == 0 && NCB <= 12 && RB % 2 == 0, "two wave columns, two wave rows");
+  constexpr int KC = 32, RBW = RB / 2, CBW = NCB / 2;
   static_assert((2 * RB) % 4 == 0, "operator blocks are dealt evenly to the four waves");
   constexpr int A_PER_W = 2 * RB / 4;
-  constexpr int BLK = 16 * KC;  // elements of a 1 KB block
-  constexpr int STAGE = Cfg::A_ELEMS + Cfg::B_ELEMS;
+  constexpr int B_PER_W = (NCB + 3) / 4;   // column blocks per wave (the last may be absent)
+  constexpr int BLK = 16 * KC;              // elements of a 1 KB block
+  constexpr int A_PART = RB * 16 * KC;      // operator part table of a stage
+  constexpr int B_PART = NCB * 16 * KC;     // density part table of a stage
+  constexpr int A_ELEMS = 2 * A_PART, STAGE = A_ELEMS + 2 * B_PART;
+  constexpr int EPC = 8;                    // elements per 16-byte chunk
+  // chunk of a 64-byte row, XOR-swizzled so that a fragment read (lane =
+  // row, one chunk column) meets no bank conflicts
+  auto swz = [](int row, int chunk) __attribute__((always_inline)) { return chunk ^ ((row >> 1) & 3); };
+  auto off = [&](int row, int chunk) __attribute__((always_inline)) { return row * KC + swz(row, chunk) * EPC; };
   using vec8 = typename std::conditional<MODE == GM_H3, f16x8, bf16x8>::type;
   __shared__ __align__(16) TA stage0[STAGE];
   __shared__ __align__(16) TA stage1[STAGE];
-  __shared__ int s_ops[kMaxTileSteps];
   float out_scale = 1.0f;
   if constexpr (MODE == GM_H3) out_scale = ldexpf(1.0f, -f16_density_exp(a.absmax) - kF16OpExp);
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int wr = wave >> 1, wc = wave & 1;
   const int tile = blockIdx.x;
-  const int row0 = blockIdx.y * Cfg::ROWS;
+  const int row0 = blockIdx.y * RB * 16;
   const int nrb = min(RB, (a.ld - row0) / 16);
   const int ld = a.ld;
   const int ncols = a.TB * a.n_rhs;
@@ -2024,35 +2032,37 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
     const int q = wave + 4 * j, t = q / RB, rb = q % RB;
     const int rl = rb * 16 + (lane >> 2);
     const int rg = min(row0 + rl, ld - 1);
-    a_goff[j] = uint32_t(rg * ld * 2 + t * KC + Cfg::swz(rl, lane & 3) * Cfg::EPC);
-    a_dst[j] = t * Cfg::A_TSTRIDE + rb * BLK;
+    a_goff[j] = uint32_t(rg * ld * 2 + t * KC + swz(rl, lane & 3) * EPC);
+    a_dst[j] = t * A_PART + rb * BLK;
   }
-  // density blocks: column slots 64 m + 16 wave + lane / 4 of the tile
-  int slot[CB];
-  uint32_t b_chunk[CB];
+  // density blocks: column slots 16 (wave + 4 m) + lane / 4 of the tile
+  int slot[B_PER_W];
+  uint32_t b_chunk[B_PER_W];
 #pragma unroll
-  for (int m = 0; m < CB; ++m) {
-    slot[m] = 64 * m + wave * 16 + (lane >> 2);
-    b_chunk[m] = uint32_t(Cfg::swz(slot[m], lane & 3));
+  for (int m = 0; m < B_PER_W; ++m) {
+    slot[m] = 16 * (wave + 4 * m) + (lane >> 2);
+    b_chunk[m] = uint32_t(swz(slot[m], lane & 3));
   }
+  auto has_block = [&](int m) __attribute__((always_inline)) { return wave + 4 * m < NCB; };
   const uint32_t col_units = uint32_t(ld * 2 * int(sizeof(TA)) / 16);  // 16-byte units per column
-  uint32_t b_goff[CB];  // 16-byte unit of the slot's column, chunk 0, part 0
+  uint32_t b_goff[B_PER_W];  // 16-byte unit of the slot's column, chunk 0, part 0
   // Step and chunk of the next chunk to request.  The operator index and the
   // source boxes of the following step are fetched a whole step ahead (the
   // step's loads complete at a handover, before they are used).  Slots past
   // the tile's columns load the last column's boxes: they only feed output
   // columns that the epilogue drops.
-  int ld_st = sb, ld_kc = 0, cur_op = 0, nxt_op = 0, nxt_src[CB];
+  int ld_st = sb, ld_kc = 0, cur_op = 0, nxt_op = 0, nxt_src[B_PER_W];
   auto fetch_step = [&](int st) __attribute__((always_inline)) {
     const int sc = min(st, se - 1);
-    nxt_op = s_ops[sc - sb];
+    nxt_op = a.step_op[sc];
 #pragma unroll
-    for (int m = 0; m < CB; ++m) nxt_src[m] = a.step_src[int64_t(sc) * a.TB + min(slot[m] / a.n_rhs, a.TB - 1)];
+    for (int m = 0; m < B_PER_W; ++m)
+      nxt_src[m] = a.step_src[int64_t(sc) * a.TB + min(slot[m] / a.n_rhs, a.TB - 1)];
   };
   auto begin_step = [&]() __attribute__((always_inline)) {
     cur_op = nxt_op;
 #pragma unroll
-    for (int m = 0; m < CB; ++m)
+    for (int m = 0; m < B_PER_W; ++m)
       b_goff[m] = (uint32_t(nxt_src[m]) * uint32_t(a.n_rhs) + uint32_t(slot[m] % a.n_rhs)) * col_units + b_chunk[m];
   };
   auto advance = [&]() __attribute__((always_inline)) {
@@ -2071,12 +2081,14 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
     for (int j = 0; j < A_PER_W; ++j)
       __builtin_amdgcn_global_load_lds((void*)(opb + a_goff[j]), (void*)(st + a_dst[j]), 16, 0, 0);
 #pragma unroll
-    for (int m = 0; m < CB; ++m) {
-      const u32x4* inb = static_cast<const u32x4*>(a.in) + b_goff[m] + uint32_t(ld_kc * 8);
+    for (int m = 0; m < B_PER_W; ++m) {
+      if (has_block(m)) {
+        const u32x4* inb = static_cast<const u32x4*>(a.in) + b_goff[m] + uint32_t(ld_kc * 8);
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
-        __builtin_amdgcn_global_load_lds((void*)(inb + 4 * t),
-                                         (void*)(st + Cfg::A_ELEMS + t * Cfg::B_TSTRIDE + (4 * m + wave) * BLK), 16, 0, 0);
+        for (int t = 0; t < 2; ++t)
+          __builtin_amdgcn_global_load_lds((void*)(inb + 4 * t),
+                                           (void*)(st + A_ELEMS + t * B_PART + (wave + 4 * m) * BLK), 16, 0, 0);
+      }
     }
   };
   // this wave's loads have landed, then every wave's (and every wave is done
@@ -2097,19 +2109,19 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
     // the loads issued before stay ahead of this chunk's work
     __builtin_amdgcn_sched_barrier(0);
     const TA* As = decltype(S)::value == 0 ? stage0 : stage1;
-    const TA* Bs = As + Cfg::A_ELEMS;
+    const TA* Bs = As + A_ELEMS;
     vec8 bh[CBW], bl[CBW], ah[RBW], al[RBW];
 #pragma unroll
     for (int c = 0; c < CBW; ++c) {
-      const int o = Cfg::off(wc * 16 * CBW + c * 16 + r16, g);
+      const int o = off(wc * 16 * CBW + c * 16 + r16, g);
       bh[c] = *reinterpret_cast<const vec8*>(Bs + o);
-      bl[c] = *reinterpret_cast<const vec8*>(Bs + Cfg::B_TSTRIDE + o);
+      bl[c] = *reinterpret_cast<const vec8*>(Bs + B_PART + o);
     }
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
-      const int o = Cfg::off((wr * RBW + i) * 16 + r16, g);
+      const int o = off((wr * RBW + i) * 16 + r16, g);
       ah[i] = *reinterpret_cast<const vec8*>(As + o);
-      al[i] = *reinterpret_cast<const vec8*>(As + Cfg::A_TSTRIDE + o);
+      al[i] = *reinterpret_cast<const vec8*>(As + A_PART + o);
     }
     // per accumulator A_h x_h, A_l x_h, A_h x_l (gemm_kernel's order);
     // consecutive products go to different accumulators
@@ -2128,8 +2140,6 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
   };
 
   if (nchunks > 0) {
-    for (int i = tid; i < se - sb; i += NT) s_ops[i] = a.step_op[sb + i];
-    __syncthreads();
     fetch_step(sb);
     begin_step();
     fetch_step(sb + 1);
@@ -2180,7 +2190,7 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
   }
 }
 
-// Split-precision M2L plans of up to 128 columns run m2l_async_kernel (1) or
+// Split-precision M2L plans of up to 160 columns run m2l_async_kernel (1) or
 // gemm_kernel (0); the two give bitwise equal results.
 static bool g_m2l_async = true;
 void set_m2l_async(bool on) { g_m2l_async = on; }
@@ -2227,19 +2237,19 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
     raise(KIFMM_EUNSUPPORTED, "GEMM operand beyond 64 GiB (boxes x right-hand sides x rows)");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
              P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
-  // split-precision M2L tiles of up to 128 columns: the asynchronous-staging
+  // split-precision M2L tiles of up to 160 columns: the asynchronous-staging
   // kernel or (65..128 columns) the wide-tile kernel
   if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && TAG == 1) {
-    if (g_m2l_async && ncols <= 128 && P.atomic) {
+    if (g_m2l_async && ncols <= 160 && P.atomic) {
       const dim3 g128(P.ntile, (ld + 127) / 128), g160(P.ntile, (ld + kROWS - 1) / kROWS);
-      const bool r128 = m2l_block_rows(ld) == 128;
-      if (ncols <= 64) {
-        if (r128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, 1>), g128, dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, 1>), g160, dim3(256), 0, s, g);
-      } else {
-        if (r128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, 2>), g128, dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, 2>), g160, dim3(256), 0, s, g);
-      }
+      auto launch = [&](auto ncb) {
+        constexpr int NCB = decltype(ncb)::value;
+        if (m2l_block_rows(ld) == 128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, NCB>), g128, dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, NCB>), g160, dim3(256), 0, s, g);
+      };
+      if (ncols <= 64) launch(std::integral_constant<int, 4>());
+      else if (ncols <= 128) launch(std::integral_constant<int, 8>());
+      else launch(std::integral_constant<int, 10>());
       LAUNCHCHECK("m2l_async_kernel");
       ps.launches++;
       return;

@@ -332,15 +332,20 @@ HostForest* build_forest(const HostTree* const* trees, int n, const HostOps& ops
         Part a{tile, {whole.opl.begin(), whole.opl.begin() + h}, {whole.srcs.begin(), whole.srcs.begin() + h}, whole.cls};
         Part b{tile, {whole.opl.begin() + h, whole.opl.end()}, {whole.srcs.begin() + h, whole.srcs.end()}, whole.cls};
         q[whole.cls].push_back(std::move(a));
-        q[whole.cls].push_back(std::move(b));
+        q[whole.cls ^ 4].push_back(std::move(b));
       } else {
         q[whole.cls].push_back(std::move(whole));
       }
     }
     // Launch order: blocks are dealt to the 8 XCDs round-robin, so part t is
-    // given octant class t % 8 while every class has parts left: the blocks
-    // resident on one XCD then walk the same operator sequence and share it
-    // through that XCD's L2.  Inside a class, parts with more steps go first.
+    // taken from queue t % 8 while every queue has parts left.  Queue k holds
+    // the even-x parts of octant k and the odd-x parts of octant k ^ 4: a
+    // step of offset parity class c reads source boxes of parity class
+    // octant ^ c, so both kinds of part sweep the same four source classes
+    // in the same order (k, k ^ 1, k ^ 2, k ^ 3), and the blocks resident on
+    // one XCD read one class of densities at a time from that XCD's L2
+    // (queued by octant alone, the two halves of a tile would keep two
+    // classes live).  Inside a queue, parts with more steps go first.
     for (auto& v : q)
       std::stable_sort(v.begin(), v.end(), [](const Part& x, const Part& y) { return x.opl.size() > y.opl.size(); });
     std::array<size_t, 8> pos{};

@@ -196,7 +196,7 @@ def test_error_paths():
 def test_tuning_keys_validated():
     """Every tuning key accepts its documented values and rejects others
     (host only: a value takes effect at the next evaluate)."""
-    good = {"m2l_tile_cols": (64, 128, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
+    good = {"m2l_tile_cols": (64, 128, 160, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
             "near_fork": (0, 1, 2, 3, 4), "graph": (0, 1), "m2l_fp64_sum_min_p": (2, 10, 17),
             "m2l_check_min_p": (2, 10, 17), "far_fp64_min_p": (2, 10, 17), "m2l_wide": (0, 1),
             "m2l_rows": (0, 128, 160), "m2l_async": (0, 1)}

@@ -78,10 +78,11 @@ def test_autotuned_layout_keeps_the_results(name, precision, tmp_path):
 
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_128_column_tiles_equal_64(name, precision):
+@pytest.mark.parametrize("width", [128, 160])
+def test_wider_column_tiles_equal_64(name, precision, width):
     tree, ops, qd, want = setup(name)
     narrow = run(tree, ops, qd, precision)
-    K.set_tuning("m2l_tile_cols", 128)
+    K.set_tuning("m2l_tile_cols", width)
     try:
         wide = run(tree, ops, qd, precision)
     finally:

@@ -318,12 +318,12 @@ def test_wide_tile_kernel_equals_gemm_kernel(case, precision):
                                   ("uniform3k_d3_p4_sparse", 1), ("clustered8k_nc24_p5", 1), ("p8", 1),
                                   ("p7", 2)])
 @pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp64+m2l_f16x3"])
-@pytest.mark.parametrize("width", [64, 128])
+@pytest.mark.parametrize("width", [64, 128, 160])
 def test_async_staging_kernel_equals_gemm_kernel(case, precision, width):
     """The split M2L kernel that stages chunks straight from global memory into
-    LDS (plans of 64 and 128 columns) gives gemm_kernel's results bitwise: the
-    same plans, products and per-column summation order.  Cases: 1, 2 and 3
-    right-hand sides (ragged columns: tiles of 21 or 42 boxes), operators
+    LDS (plans of 64, 128 and 160 columns) gives gemm_kernel's results bitwise:
+    the same plans, products and per-column summation order.  Cases: 1, 2 and 3
+    right-hand sides (ragged columns: tiles of 21, 42 or 53 boxes), operators
     shorter than the block (p = 4), 128-row blocks (p = 5, 7), two row blocks
     (p = 8), adaptive trees, FP64 outputs."""
     name, n_rhs = case
