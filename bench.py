@@ -381,6 +381,14 @@ def main():
     flops_m2l = 2.0 * pn * pn * v_pairs * n_rhs
     leaf_pairs = (near_pairs + far_pairs) * n_rhs
     pair_stage = launches.get("m2l_pair", 0.0) > 0
+    # the split M2L runs the LDS-staged kernel for tiles of up to 160 columns
+    # with FP32 sums (below m2l_fp64_sum_min_p); with FP64 sums, up to 96
+    # columns in 128-row blocks or 64 in 160-row blocks; otherwise gemm_kernel
+    ld = (pn + 31) // 32 * 32
+    rows = K.get_tuning("m2l_rows") or (128 if (ld + 127) // 128 * 128 < (ld + 159) // 160 * 160 else 160)
+    fp64_sums = prob.p >= K.get_tuning("m2l_fp64_sum_min_p")
+    async_m2l = (layout["m2l_async"] == 1
+                 and layout["m2l_tile_cols"] <= ((96 if rows == 128 else 64) if fp64_sums else 160))
     if dom == "m2l_pair" or (dom == "m2l" and pair_stage):
         # sparse (adaptive) problems run M2L pair by pair: the algorithmic
         # flops over the whole M2L stage (gathered tiles, pair tiles, pair sums)
@@ -389,7 +397,8 @@ def main():
                 "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
         issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
         t_stage = (ms["m2l"] + ms["m2l_pair"]) * 1e-3
-        roof = {"kernel": "M2L stage (gemm_kernel gathered + pair tiles, m2l_pair_sum_kernel)",
+        gk = "m2l_async_kernel" if m2l_kind in ("bf16x3", "f16x3") and async_m2l else "gemm_kernel"
+        roof = {"kernel": f"M2L stage ({gk} gathered + pair tiles, m2l_pair_sum_kernel)",
                 "bound": "mfma", "achieved": flops_m2l / t_stage / 1e12, "peak": peak / 1e12,
                 "unit": "TFLOP/s", "issued_frac": issued * flops_m2l / t_stage / peak}
     elif dom == "m2l":
@@ -399,8 +408,7 @@ def main():
         peak = {"fp64": PEAK_FP64_MFMA, "fp32": PEAK_FP32_MFMA,
                 "bf16x3": PEAK_BF16_MFMA, "bf16x5": PEAK_BF16_MFMA, "f16x3": PEAK_BF16_MFMA}[m2l_kind]
         issued = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x5": 5, "f16x3": 3}[m2l_kind]
-        split_m2l = m2l_kind in ("bf16x3", "f16x3") and layout["m2l_tile_cols"] <= 160
-        name = "m2l_async_kernel" if split_m2l and layout["m2l_async"] else "gemm_kernel"
+        name = "m2l_async_kernel" if m2l_kind in ("bf16x3", "f16x3") and async_m2l else "gemm_kernel"
         roof = {"kernel": f"{name} (M2L)", "bound": "mfma",
                 "achieved": flops_m2l / (ms["m2l"] / launches["m2l"] * 1e-3) / 1e12,
                 "peak": peak / 1e12, "unit": "TFLOP/s",

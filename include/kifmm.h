@@ -334,7 +334,7 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
 /* Process-wide tuning knobs of the evaluation kernels (a change of a plan
  * knob rebuilds the plans at the next evaluate).
  *   "m2l_tile_cols":  output columns (box x right-hand side) per M2L tile,
- *                     64 (default), 128, 160 or 192.  Above 128, M2L kernels
+ *                     64 (default), 96, 128, 160 or 192.  Above 128, M2L kernels
  *                     with 32-bit outputs run one 768-thread block per tile
  *                     (split modes up to 160 columns: the kernel of
  *                     m2l_async); the others cover the tile with 64-column
@@ -381,12 +381,14 @@ kifmm_status kifmm_debug_buffer(const kifmm_tree* tree, int32_t which, int32_t f
  *                     general gathered-GEMM kernel.  Results are bitwise
  *                     equal.
  *   "m2l_async":      1 (default): split-BF16 and split-FP16 M2L plans of
- *                     up to 160 columns (m2l_tile_cols 64, 128, 160) run a
- *                     kernel that stages operator and density chunks from
- *                     global memory straight into LDS, two chunks in
- *                     flight; 0: the general gathered-GEMM kernel (and, with
- *                     m2l_wide, the wide-tile kernel).  Results are bitwise
- *                     equal.
+ *                     up to 160 columns (m2l_tile_cols 64, 128, 160; the
+ *                     gathered tiles and the pair tiles; with FP64 sums, see
+ *                     m2l_fp64_sum_min_p, up to 96 columns in blocks of 128
+ *                     operator rows, else 64) run a kernel that
+ *                     stages operator and density chunks from global memory
+ *                     straight into LDS, two chunks in flight; 0: the
+ *                     general gathered-GEMM kernel (and, with m2l_wide, the
+ *                     wide-tile kernel).  Results are bitwise equal.
  *   "m2l_rows":       operator rows per M2L block: 160, 128, or 0 (default)
  *                     for the one that pads the operator's rows (n rounded
  *                     up to 32) the least: 128 at p = 4, 5, 7, 10.  Results

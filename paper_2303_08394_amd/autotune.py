@@ -1,7 +1,7 @@
 """Measured choice of an evaluation's launch layout.
 
 The layout knobs of ``kifmm_set_tuning`` change how an evaluation is cut into
-kernel launches, not the method: the M2L tile width (64, 128, 160 or 192 output
+kernel launches, not the method: the M2L tile width (64, 96, 128, 160 or 192 output
 columns per block; results bitwise equal), whether each M2L tile runs as one
 block or as two parity parts, the tile-fill threshold below which a problem's
 M2L runs pair by pair, where the near field sits in the schedule, and the
@@ -34,7 +34,7 @@ from . import kifmm as K
 # The searched knobs and their candidates, in search order.  The first
 # candidate of each is its library default.
 SPACE: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
-    ("m2l_tile_cols", (64, 128, 160, 192)),
+    ("m2l_tile_cols", (64, 96, 128, 160, 192)),
     # the split M2L kernel: staging straight into LDS (1) or through registers
     ("m2l_async", (1, 0)),
     ("m2l_split", (1, 0)),

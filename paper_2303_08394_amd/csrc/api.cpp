@@ -525,8 +525,8 @@ kifmm_status kifmm_set_tuning(const char* key, int32_t value) {
 
 static kifmm_status set_tuning_impl(const char* key, int32_t value) {
   if (std::strcmp(key, "m2l_tile_cols") == 0) {
-    if (value != 64 && value != 128 && value != 160 && value != 192)
-      return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64, 128, 160 or 192");
+    if (value != 64 && value != 96 && value != 128 && value != 160 && value != 192)
+      return fail(KIFMM_EINVAL, "set_tuning: m2l_tile_cols must be 64, 96, 128, 160 or 192");
     g_m2l_tile_cols = value;
     return KIFMM_OK;
   }

@@ -1250,6 +1250,7 @@ struct GemmArgs {
   const unsigned* absmax;  // FP16 split: bits of max |input| (non-negative float)
   int zero_box;            // box index of the all-zero columns (the forest's nbox)
   int atomic;              // add into the output with atomics (see Plan::atomic)
+  int ntile;               // tiles of the plan
 };
 
 constexpr int kRB = 10, kROWS = kRB * 16;
@@ -1967,7 +1968,8 @@ __global__ __launch_bounds__(256, 2) void m2l_wide_kernel(GemmArgs a) {
 // fragments of its chunk first and then issues its MFMAs back to back.
 // Block shape (four waves in a 2 x 2 grid, wave tiles of 8 RB x 8 NCB), plans,
 // arithmetic and summation order per column are gemm_kernel's, so the
-// results are bitwise equal to it.
+// results are bitwise equal to it.  Gathered tiles add into the output with
+// atomics (two terms a value); pair tiles store their products.
 //
 // LDS traffic is arranged in 1 KB blocks (16 rows or columns of one part,
 // 64 bytes each): a stage holds 2 RB operator blocks and 2 NCB density
@@ -1977,7 +1979,7 @@ __global__ __launch_bounds__(256, 2) void m2l_wide_kernel(GemmArgs a) {
 // writes one block, lane i to its 16-byte slot i, so each lane fetches the
 // global chunk that the XOR swizzle of the layout puts in that slot (the
 // swizzle is an involution).
-template <int MODE, class TO, int RB, int NCB>
+template <int MODE, class TO, int RB, int NCB, bool FLUSH = false>
 __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
   using G = GT<MODE>;
   using TA = typename G::TA;
@@ -2005,8 +2007,17 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, g = lane >> 4, r16 = lane & 15;
   const int wr = wave >> 1, wc = wave & 1;
-  const int tile = blockIdx.x;
-  const int row0 = blockIdx.y * RB * 16;
+  // Blocks are dealt to the 8 XCDs round-robin.  The grid is 1-D over the
+  // tiles (padded to a multiple of 8) times the row blocks, row block
+  // slowest, numbered so that XCD x receives tiles x, x + 8, ... (the plan's
+  // XCD queues) in every row block: the blocks running together then share
+  // one row slice of each operator.  (Running a tile's row blocks together
+  // instead, to share its density columns, measured slower.)
+  const int T8 = (a.ntile + 7) / 8;  // groups of 8 tiles
+  const int xcd = int(blockIdx.x & 7), kx = int(blockIdx.x >> 3);
+  const int tile = (kx % T8) * 8 + xcd;
+  if (tile >= a.ntile) return;  // padding of the last group of 8 tiles
+  const int row0 = (kx / T8) * RB * 16;
   const int nrb = min(RB, (a.ld - row0) / 16);
   const int ld = a.ld;
   const int ncols = a.TB * a.n_rhs;
@@ -2021,6 +2032,17 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
     for (int c = 0; c < CBW; ++c)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][c][v] = 0.0f;
+  // FLUSH (FP64 sums, as gemm_kernel's TAG 2): after every operator step the
+  // FP32 sums move into FP64 registers
+  f64x4 acc64[FLUSH ? RBW : 1][FLUSH ? CBW : 1];
+  if constexpr (FLUSH) {
+#pragma unroll
+    for (int i = 0; i < RBW; ++i)
+#pragma unroll
+      for (int c = 0; c < CBW; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[i][c][v] = 0.0;
+  }
 
   // operator blocks of this wave: element offsets in an operator (chunk 0)
   // and the blocks' places in a stage.  Rows past ld are clamped to a valid
@@ -2139,6 +2161,24 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
     __builtin_amdgcn_sched_group_barrier(0x008, 3 * CBW * RBW, 0);
   };
 
+  int cm_kc = 0;  // chunk within the step, on the compute side
+  auto step_end = [&]() __attribute__((always_inline)) {
+    if constexpr (FLUSH) {
+      if (++cm_kc == kcs) {
+        cm_kc = 0;
+#pragma unroll
+        for (int i = 0; i < RBW; ++i)
+#pragma unroll
+          for (int c = 0; c < CBW; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              acc64[i][c][v] += double(acc[i][c][v]);
+              acc[i][c][v] = 0.0f;
+            }
+      }
+    }
+  };
+
   if (nchunks > 0) {
     fetch_step(sb);
     begin_step();
@@ -2152,16 +2192,19 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
       advance();
       issue(S1);
       compute(S0);
+      step_end();
       handover();
       if (c + 2 < nchunks) {
         advance();
         issue(S0);
       }
       compute(S1);
+      step_end();
     }
     if (c < nchunks) {
       handover();
       compute(S0);
+      step_end();
     }
   }
 
@@ -2177,11 +2220,29 @@ __global__ __launch_bounds__(256, 2) void m2l_async_kernel(GemmArgs a) {
         for (int i = 0; i < RBW; ++i) {
           if (wr * RBW + i < nrb) {
             const int rbase = row0 + (wr * RBW + i) * 16;
+            // summed in the wider of FP32 and the output type (gemm_kernel's rule)
+            using TAcc = typename std::conditional<(sizeof(TO) > 4), TO, float>::type;
+            TAcc val[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              float val = acc[i][cb][v];
-              if constexpr (MODE == GM_H3) val *= out_scale;
-              unsafeAtomicAdd(o + rbase + G::row(lane, v), TO(val));
+              val[v] = TAcc(acc[i][cb][v]);
+              if constexpr (FLUSH) val[v] = TAcc(acc64[i][cb][v] + double(acc[i][cb][v]));
+              if constexpr (MODE == GM_H3) val[v] *= TAcc(out_scale);
+            }
+            if (a.atomic) {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) unsafeAtomicAdd(o + rbase + G::row(lane, v), TO(val[v]));
+            } else if constexpr (sizeof(TO) == 4) {
+              // pair tiles: every output written once; the lane's four rows
+              // are consecutive, one 16-byte store
+              static_assert(G::ROWS4, "four consecutive rows a lane");
+              f32x4 w;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) w[v] = float(val[v]);
+              *reinterpret_cast<f32x4*>(o + rbase + G::row(lane, 0)) = w;
+            } else {
+#pragma unroll
+              for (int v = 0; v < 4; ++v) o[rbase + G::row(lane, v)] = TO(val[v]);
             }
           }
         }
@@ -2236,24 +2297,39 @@ static void run_gemm(const DevPlan& P, const void* ops, int64_t op_stride, int l
   if (gemm_in_units<MODE, TI>(zero_box, n_rhs, ld) > (uint64_t(1) << 32))
     raise(KIFMM_EUNSUPPORTED, "GEMM operand beyond 64 GiB (boxes x right-hand sides x rows)");
   GemmArgs g{ops, op_stride, ld, n_rhs, accumulate ? 1 : 0, P.TB, in, out,
-             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0};
-  // split-precision M2L tiles of up to 160 columns: the asynchronous-staging
-  // kernel or (65..128 columns) the wide-tile kernel
-  if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && TAG == 1) {
-    if (g_m2l_async && ncols <= 160 && P.atomic) {
-      const dim3 g128(P.ntile, (ld + 127) / 128), g160(P.ntile, (ld + kROWS - 1) / kROWS);
+             P.tile_cols, P.step_beg, P.step_op, P.step_src, absmax, zero_box, P.atomic ? 1 : 0,
+             int(P.ntile)};
+  // split-precision M2L tiles of up to 160 columns (gathered tiles adding
+  // with atomics, or pair tiles storing their products): the
+  // asynchronous-staging kernel or (65..128 columns) the wide-tile kernel
+  if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && (TAG == 1 || TAG == 2)) {
+    // with FP64 sums (TAG 2) the FP64 accumulators fit the registers of
+    // tiles of up to 96 columns (128-row blocks) or 64 (160-row blocks)
+    constexpr bool FL = TAG == 2;
+    const bool r128 = m2l_block_rows(ld) == 128;
+    if (g_m2l_async && ncols <= (FL ? (r128 ? 96 : 64) : 160) && (P.atomic || !accumulate)) {
+      // 1-D grids: tiles padded to a multiple of 8, times the row blocks
+      const unsigned t8 = unsigned((P.ntile + 7) / 8 * 8);
+      const dim3 g128(t8 * unsigned((ld + 127) / 128)), g160(t8 * unsigned((ld + kROWS - 1) / kROWS));
       auto launch = [&](auto ncb) {
         constexpr int NCB = decltype(ncb)::value;
-        if (m2l_block_rows(ld) == 128) hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, NCB>), g128, dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, NCB>), g160, dim3(256), 0, s, g);
+        if constexpr (!FL || NCB <= 6) {
+          if (r128)
+            hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, 8, NCB, FL>), g128, dim3(256), 0, s, g);
+          else if constexpr (!FL || NCB == 4)
+            hipLaunchKernelGGL((m2l_async_kernel<MODE, TO, kRB, NCB, FL>), g160, dim3(256), 0, s, g);
+        }
       };
       if (ncols <= 64) launch(std::integral_constant<int, 4>());
+      else if (ncols <= 96) launch(std::integral_constant<int, 6>());
       else if (ncols <= 128) launch(std::integral_constant<int, 8>());
       else launch(std::integral_constant<int, 10>());
       LAUNCHCHECK("m2l_async_kernel");
       ps.launches++;
       return;
     }
+  }
+  if constexpr ((MODE == GM_BF3 || MODE == GM_H3) && TAG == 1) {
     if (g_m2l_wide && ncols > 64 && ncols <= 128 && P.atomic) {
       dim3 grid(P.ntile, (ld + kROWS - 1) / kROWS);
       hipLaunchKernelGGL((m2l_wide_kernel<MODE, TO>), grid, dim3(256), 0, s, g);

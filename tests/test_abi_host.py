@@ -196,11 +196,11 @@ def test_error_paths():
 def test_tuning_keys_validated():
     """Every tuning key accepts its documented values and rejects others
     (host only: a value takes effect at the next evaluate)."""
-    good = {"m2l_tile_cols": (64, 128, 160, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
+    good = {"m2l_tile_cols": (64, 96, 128, 160, 192), "m2l_split": (0, 1), "m2l_pair_fill": (0, 40, 101),
             "near_fork": (0, 1, 2, 3, 4), "graph": (0, 1), "m2l_fp64_sum_min_p": (2, 10, 17),
             "m2l_check_min_p": (2, 10, 17), "far_fp64_min_p": (2, 10, 17), "m2l_wide": (0, 1),
             "m2l_rows": (0, 128, 160), "m2l_async": (0, 1)}
-    bad = {"m2l_tile_cols": (0, 96, 256), "m2l_split": (2, -1), "m2l_pair_fill": (-1, 102),
+    bad = {"m2l_tile_cols": (0, 80, 256), "m2l_split": (2, -1), "m2l_pair_fill": (-1, 102),
            "near_fork": (-1, 5), "graph": (2,), "m2l_fp64_sum_min_p": (1, 18),
            "m2l_check_min_p": (1, 18), "far_fp64_min_p": (1, 18), "m2l_wide": (2, -1),
            "m2l_rows": (96, 1, -1), "m2l_async": (2, -1)}

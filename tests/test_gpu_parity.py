@@ -318,10 +318,10 @@ def test_wide_tile_kernel_equals_gemm_kernel(case, precision):
                                   ("uniform3k_d3_p4_sparse", 1), ("clustered8k_nc24_p5", 1), ("p8", 1),
                                   ("p7", 2)])
 @pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp64+m2l_f16x3"])
-@pytest.mark.parametrize("width", [64, 128, 160])
+@pytest.mark.parametrize("width", [64, 96, 128, 160])
 def test_async_staging_kernel_equals_gemm_kernel(case, precision, width):
     """The split M2L kernel that stages chunks straight from global memory into
-    LDS (plans of 64, 128 and 160 columns) gives gemm_kernel's results bitwise:
+    LDS (plans of 64, 96, 128 and 160 columns) gives gemm_kernel's results bitwise:
     the same plans, products and per-column summation order.  Cases: 1, 2 and 3
     right-hand sides (ragged columns: tiles of 21, 42 or 53 boxes), operators
     shorter than the block (p = 4), 128-row blocks (p = 5, 7), two row blocks
@@ -343,6 +343,69 @@ def test_async_staging_kernel_equals_gemm_kernel(case, precision, width):
         got = gpu_eval(tree, p, qm, precision)
     finally:
         K.set_tuning("m2l_async", 1)
+        K.set_tuning("m2l_tile_cols", 64)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("case", [("uniform20k_d3_p6", 1), ("uniform20k_d3_p6", 3), ("clustered8k_nc24_p5", 1),
+                                  ("p8", 2), ("p10", 1)])
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3", "fp64+m2l_f16x3"])
+@pytest.mark.parametrize("width", [64, 96])
+def test_async_staging_kernel_with_fp64_sums(case, precision, width):
+    """With FP64 sums after every operator step (the default from p = 10; here
+    forced from p = 2 on), M2L tiles of 64 and 96 columns staged straight into
+    LDS give gemm_kernel's results bitwise: the same per-step FP32 sums, moved
+    into FP64 at the same points (96 columns with 128-row blocks only; with
+    160-row blocks such tiles run gemm_kernel).  Cases: 1, 2, 3 right-hand
+    sides, 128-row blocks (p = 5, 10), two row blocks (p = 8), an adaptive
+    tree."""
+    name, n_rhs = case
+    if name in ("p8", "p10"):
+        x, q = I.uniform_cube(12000 if name == "p8" else 6000, seed=36, charge_range=(-1, 1))
+        tgt, p, kw = None, int(name[1:]), dict(uniform_depth=3, **CUBE)
+    else:
+        x, q, tgt, p, kw = CASES[name]()
+    tree = K.Tree(x, tgt, **kw)
+    qm = np.vstack([np.atleast_2d(q)] + [np.random.default_rng(50 + r).uniform(-1, 1, (1, len(x)))
+                                         for r in range(n_rhs - 1)])
+    K.set_tuning("m2l_fp64_sum_min_p", 2)
+    K.set_tuning("m2l_tile_cols", width)
+    try:
+        K.set_tuning("m2l_async", 0)
+        ref = gpu_eval(tree, p, qm, precision)
+        K.set_tuning("m2l_async", 1)
+        got = gpu_eval(tree, p, qm, precision)
+    finally:
+        K.set_tuning("m2l_async", 1)
+        K.set_tuning("m2l_fp64_sum_min_p", 10)
+        K.set_tuning("m2l_tile_cols", 64)
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("name", ["sphere12k_nc32_p6", "uniform3k_d3_p4_sparse", "p8"])
+@pytest.mark.parametrize("precision", ["bf16x3", "f16x3"])
+@pytest.mark.parametrize("width", [64, 128, 160])
+def test_async_staging_kernel_on_pair_tiles(name, precision, width):
+    """M2L run pair by pair: the pair tiles (one offset each, products stored
+    to the pair buffer, not added) staged straight into LDS give gemm_kernel's
+    pair products, hence the same potentials bitwise.  Operators of one and
+    two row blocks (p = 4, 6; p = 8), ragged last tiles."""
+    if name == "p8":
+        x, q = I.uniform_cube(12000, seed=35, charge_range=(-1, 1))
+        tgt, p, kw = None, 8, dict(uniform_depth=3, **CUBE)
+    else:
+        x, q, tgt, p, kw = CASES[name]()
+    tree = K.Tree(x, tgt, **kw)
+    K.set_tuning("m2l_tile_cols", width)
+    K.set_tuning("m2l_pair_fill", 101)  # every problem pair by pair
+    try:
+        K.set_tuning("m2l_async", 0)
+        ref = gpu_eval(tree, p, q, precision)
+        K.set_tuning("m2l_async", 1)
+        got = gpu_eval(tree, p, q, precision)
+    finally:
+        K.set_tuning("m2l_async", 1)
+        K.set_tuning("m2l_pair_fill", 40)
         K.set_tuning("m2l_tile_cols", 64)
     np.testing.assert_array_equal(got, ref)
 
