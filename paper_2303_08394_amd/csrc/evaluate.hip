@@ -705,8 +705,10 @@ __global__ void zero_kernel(uint4* __restrict__ p, int64_t n16) {
 // (P2M: upward check, P2L: downward check); sources are "segments": the
 // particles of a leaf, or the equivalent surface of a box with its density.
 // Every source is moved into the target box's frame once, while it is staged
-// into LDS; targets are split into chunks of TCH lanes and the SL = 256/TCH
-// lane groups ("slices") stride over the staged sources, then reduce in FP64.
+// into LDS; targets are split into chunks (64 lanes for surface targets; of
+// equal width up to 64 lanes, chosen per leaf, for particles) and the
+// 256 / width lane groups ("slices") stride over the staged sources, then
+// reduce in FP64.
 
 // LEAF: near + far in one pass; NEAR: U lists only (writes the sums);
 // FAR: W lists and the own downward surface (adds to the sums).
@@ -813,7 +815,9 @@ template <class U, class T, int MODE, int RC, int TCH, bool GRAD = false, bool S
 __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st, int wi, int B,
                           int4 gB, int nU, int s0, int s1, int rhs0, const double (&tx)[kNch],
                           const double (&ty)[kNch], const double (&tz)[kNch], int nchunks,
-                          double (&acc)[kNch][RC], double (&gacc)[kNch][3], double kB) {
+                          double (&acc)[kNch][RC], double (&gacc)[kNch][3], double kB, int j0, int SL) {
+  // j0: this lane's first staged source (its lane group; past every source
+  // for lanes outside the SL lane groups), SL: lane groups striding over them
   // SCR: the screened kernel, exp(-kB d) / d in the target box's units
   // (kB = kappa r_B); its factor multiplies 1 / d
   const U ukB = U(kB);
@@ -824,11 +828,11 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
   constexpr bool LO = GRAD && sizeof(U) == 4;
   using C = P2PCfg<U, RC, LO>;
   using V = typename V4<U>::type;
-  constexpr int NT = 256, SL = NT / TCH, CAP = C::CAP;
+  constexpr int NT = 256, CAP = C::CAP;
   V* s_pos = reinterpret_cast<V*>(smem);
   U* s_q = reinterpret_cast<U*>(smem + CAP * sizeof(V));
   V* s_lo = reinterpret_cast<V*>(smem + CAP * sizeof(V));  // (LO only, RC == 1)
-  const int tid = threadIdx.x, sl = tid / TCH;
+  const int tid = threadIdx.x;
   U ux[kNch], uy[kNch], uz[kNch], lx[kNch], ly[kNch], lz[kNch];
 #pragma unroll
   for (int c = 0; c < kNch; ++c) {
@@ -940,7 +944,7 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 #pragma unroll
           for (int r = 0; r < RC; ++r) part[r] = U(0);
           const U x = ux[c], y = uy[c], z = uz[c], xl = lx[c], yl = ly[c], zl = lz[c];
-          // sources j = sl, sl + SL, ... in order; four per trip so that their
+          // sources j = j0, j0 + SL, ... in order; four per trip so that their
           // LDS reads are in flight together (same summation order)
           auto pair = [&](const V& s, int j, auto checked) __attribute__((always_inline)) {
             U dx = x - s.x, dy = y - s.y, dz = z - s.z;
@@ -992,7 +996,7 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
           };
           const std::true_type chk;
           const std::false_type nochk;
-          // the ranges keep the order j = sl, sl + SL, ...
+          // the ranges keep the order j = j0, j0 + SL, ...
           int lo = nb, hi = nb;
           if (st.self_k >= 0) {
             lo = min(max(st.pre[st.self_k] - b0, 0), nb);
@@ -1000,19 +1004,19 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
           }
           if constexpr (MODE == MODE_LEAF || MODE == MODE_NEAR) {
             // only the target box's own particles need the coincidence test
-            int j = run(sl, lo, nochk);
+            int j = run(j0, lo, nochk);
             j = run(j, hi, chk);
             run(j, nb, nochk);
           } else if constexpr (MODE == MODE_FAR) {
             // all but the box's own downward surface need it
-            int j = run(sl, lo, chk);
+            int j = run(j0, lo, chk);
             j = run(j, hi, nochk);
             run(j, nb, chk);
           } else if constexpr (MODE == MODE_P2M) {
             // check surface at 2.95 r, sources inside the box: never coincide
-            run(sl, nb, nochk);
+            run(j0, nb, nochk);
           } else {
-            run(sl, nb, chk);
+            run(j0, nb, chk);
           }
 #pragma unroll
           for (int r = 0; r < RC; ++r) acc[c][r] += double(part[r]);
@@ -1032,13 +1036,14 @@ __device__ void p2p_phase(const P2PArgs<T>& a, unsigned char* smem, SegTable& st
 // (P2M: upward check, P2L: downward check); sources are "segments": the
 // particles of a leaf, or the equivalent surface of a box with its density.
 // Every source is moved into the target box's frame once, while it is staged
-// into LDS; targets are split into chunks of TCH lanes and the 256/TCH lane
-// groups stride over the staged sources, then reduce in FP64.  Particle
+// into LDS; targets are split into chunks (TCH lanes, or for leaves of equal
+// width chosen per leaf, see below) and the lane groups stride over the
+// staged sources, then reduce in FP64.  Particle
 // segments are computed in T, equivalent-surface segments (L2P, M2P) in TF:
 // FP64 at high order, where the equivalent densities cancel strongly.
 template <class T, class TF, int MODE, int RC, int TCH, bool GRAD = false, bool SCR = false>
 __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
-  constexpr int NT = 256, SL = NT / TCH;
+  constexpr int NT = 256;
   static_assert(!GRAD || (MODE == MODE_LEAF && RC == 1), "gradients: leaf kernel, one right-hand side");
   constexpr int SMEM0 = P2PCfg<T, RC, GRAD>::BYTES > P2PCfg<TF, RC, GRAD>::BYTES ? P2PCfg<T, RC, GRAD>::BYTES
                                                                                  : P2PCfg<TF, RC, GRAD>::BYTES;
@@ -1048,7 +1053,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
   __shared__ SegTable st;
   double* s_red = reinterpret_cast<double*>(smem);
 
-  const int tid = threadIdx.x, ti = tid % TCH, sl = tid / TCH;
+  const int tid = threadIdx.x;
   const int wi = blockIdx.x;
   const int B = a.work[wi];
   const int rhs0 = blockIdx.y * RC;
@@ -1078,12 +1083,26 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
     trad = MODE == MODE_P2M ? kRout : kRin;
   }
 
-  for (int t0 = 0; t0 < nt; t0 += TCH * kNch) {
+  // Lanes per target chunk: TCH for surface targets; for leaves, the
+  // leaf's targets in ceil(nt / 64) chunks of equal width (at least 8 lanes;
+  // 64 past kNch such chunks), so that a leaf of 33 to 64 points does not pad
+  // to 64 target slots nor one of 65 to 96 to 128.  The 256 / tch lane
+  // groups (the rest of the threads idle) stride over the staged sources.
+  // The split depends only on the box, so runs stay deterministic.  (Surface
+  // targets, 152 at p = 6, measured slower in 3 chunks of 51 than of 64.)
+  int tch = TCH;
+  if constexpr (LEAFLIKE) {
+    const int nch = (nt + 63) / 64;
+    tch = nch <= kNch ? max((nt + nch - 1) / max(nch, 1), 8) : 64;
+  }
+  const int ti = tid % tch, sl = tid / tch, SL = NT / tch;
+  const int j0 = sl < SL ? sl : (1 << 30);
+  for (int t0 = 0; t0 < nt; t0 += tch * kNch) {
     double tx[kNch], ty[kNch], tz[kNch];
     double acc[kNch][RC], gacc[kNch][3];
 #pragma unroll
     for (int c = 0; c < kNch; ++c) {
-      int t = t0 + c * TCH + ti;
+      int t = t0 + c * tch + ti;
       tx[c] = ty[c] = tz[c] = 0.0;
       if (t < nt) {
         if (LEAFLIKE) {
@@ -1103,14 +1122,14 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) gacc[c][k] = 0.0;
     }
-    const int nchunks = (min(nt - t0, TCH * kNch) + TCH - 1) / TCH;
+    const int nchunks = (min(nt - t0, tch * kNch) + tch - 1) / tch;
     const double kB = SCR ? a.kappa * a.box_r[B] : 0.0;
     if (MODE != MODE_FAR)
       p2p_phase<T, T, MODE, RC, TCH, GRAD, SCR>(a, smem, st, wi, B, gB, nU, 0, nnear, rhs0, tx, ty, tz,
-                                                nchunks, acc, gacc, kB);
+                                                nchunks, acc, gacc, kB, j0, SL);
     if (MODE != MODE_NEAR && nseg > nnear)
       p2p_phase<TF, T, MODE, RC, TCH, GRAD, SCR>(a, smem, st, wi, B, gB, nU, nnear, nseg, rhs0, tx, ty, tz,
-                                                 nchunks, acc, gacc, kB);
+                                                 nchunks, acc, gacc, kB, j0, SL);
 
     // reduce the slices of each chunk and write
     const double rB = a.box_r[B];
@@ -1119,14 +1138,14 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
       if (c < nchunks) {
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < RC; ++r) s_red[(sl * TCH + ti) * NV + r] = acc[c][r];
+        for (int r = 0; r < RC; ++r) s_red[(sl * tch + ti) * NV + r] = acc[c][r];
         if constexpr (GRAD) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k) s_red[(sl * TCH + ti) * NV + 1 + k] = gacc[c][k];
+          for (int k = 0; k < 3; ++k) s_red[(sl * tch + ti) * NV + 1 + k] = gacc[c][k];
         }
         __syncthreads();
         if (sl == 0) {
-          const int t = t0 + c * TCH + ti;
+          const int t = t0 + c * tch + ti;
           if (t < nt) {
             if constexpr (GRAD) {
               // potentials then gradients: component k of right-hand side
@@ -1138,7 +1157,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                   v[k] = 0.0;
-                  for (int s2 = 0; s2 < SL; ++s2) v[k] += s_red[(s2 * TCH + ti) * NV + k];
+                  for (int s2 = 0; s2 < SL; ++s2) v[k] += s_red[(s2 * tch + ti) * NV + k];
                 }
                 double* o = a.pot + int64_t(4 * rr) * a.ntgt + tbase + t;
                 o[0] = v[0] * (kInv4Pi / rB);
@@ -1149,7 +1168,7 @@ __global__ __launch_bounds__(256) void p2p_kernel(P2PArgs<T> a) {
 #pragma unroll
             for (int r = 0; r < RC; ++r) {
               double sum = 0.0;
-              for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * TCH + ti) * NV + r];
+              for (int s2 = 0; s2 < SL; ++s2) sum += s_red[(s2 * tch + ti) * NV + r];
               const int rr = rhs0 + r;
               if (rr < a.n_rhs) {
                 if (MODE == MODE_LEAF || MODE == MODE_NEAR) {
