@@ -67,6 +67,18 @@ def _work_counts(tree, pn):
     return int(tree.info().n_v), near, far
 
 
+def _translation_counts(tree):
+    """Box columns of the equivalent-density solves and translations: (UC2E,
+    DC2E, M2M, L2L) = (boxes of levels >= 2 with sources, with targets,
+    boxes of levels >= 3 with sources, with targets)."""
+    bx = tree.boxes()
+    lev = bx["level"]
+    ns = bx["src_range"][:, 1] - bx["src_range"][:, 0]
+    nt = bx["tgt_range"][:, 1] - bx["tgt_range"][:, 0]
+    return (int(((lev >= 2) & (ns > 0)).sum()), int(((lev >= 2) & (nt > 0)).sum()),
+            int(((lev >= 3) & (ns > 0)).sum()), int(((lev >= 3) & (nt > 0)).sum()))
+
+
 def _kernel_source_sha() -> str:
     import hashlib
     p = os.path.join(ROOT, "paper_2303_08394_amd", "csrc", "evaluate.hip")
@@ -450,6 +462,27 @@ def main():
         result["leaf_field"] = {"kernel": "p2p_kernel (near + far field)", "pairs_per_s": leaf_rate,
                                 "frac_of_valu_peak": leaf_rate / PEAK_PAIRS,
                                 "frac_of_min_op_bound": leaf_rate / PEAK_PAIRS_MIN_OPS}
+    # the equivalent-density solves (FP64 GEMMs in every mode) and the
+    # translations (FP32 GEMMs in the FP32-bulk modes, FP64 in the FP64
+    # ones): algorithmic flops (2 n^2 per box column) over the phase's time
+    # per evaluation, all levels' launches together
+    cols = np.zeros(4, np.int64)
+    for t in trees:
+        cols += np.array(_translation_counts(t), np.int64)
+    fp64_bulk = precision.startswith("fp64")
+    trans = {}
+    for k, name, c, pk in (("uc2e", "gemm_kernel<FP64>", cols[0], PEAK_FP64_MFMA),
+                           ("dc2e", "gemm_kernel<FP64>", cols[1], PEAK_FP64_MFMA),
+                           ("m2m", "gemm_kernel<FP64>" if fp64_bulk else "gemm_kernel<FP32> + m2m_sum_kernel",
+                            cols[2], PEAK_FP64_MFMA if fp64_bulk else PEAK_FP32_MFMA),
+                           ("l2l", "gemm_kernel<FP64>" if fp64_bulk else "gemm_kernel<FP32>",
+                            cols[3], PEAK_FP64_MFMA if fp64_bulk else PEAK_FP32_MFMA)):
+        if ms.get(k, 0.0) > 0.0:
+            flops = 2.0 * pn * pn * float(c) * n_rhs
+            ach = flops / (ms[k] * 1e-3)
+            trans[k] = {"kernel": name, "launches": launches[k], "flop": flops, "ms": ms[k],
+                        "achieved_tflops": ach / 1e12, "peak_tflops": pk / 1e12, "frac": ach / pk}
+    result["translation_rooflines"] = trans
     # the committed counter summaries are per M2L tile width (two parity parts
     # per tile, gathered tiles: the layouts whose M2L kernel they measured)
     m2l_counters = (args.config == "uniform_1m" and dom == "m2l" and layout["m2l_split"] == 1
